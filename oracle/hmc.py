@@ -1,0 +1,106 @@
+"""Leapfrog trajectory, Hamiltonian and Metropolis-Hastings step, in FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows Algorithms 1 and 2 of the paper:
+  draw p ~ N(0, M); integrate Hamilton's equations (Sec. 2.2) for L steps of
+  size eps; accept the end point when the ratio r of exp(-H) values exceeds a
+  uniform draw u, else keep the current point; the momentum is discarded.
+
+Readings (the paper leaves these open):
+  * kinetic energy K = p^T M^-1 p / 2: the text identifies K with the
+    Gaussian log-density of p ~ N(0, M), which carries the one half;
+  * the integrator is leapfrog in kick-drift-kick form (the text allows Euler
+    or leapfrog; only leapfrog is volume preserving and reversible, which the
+    Metropolis correction relies on);
+  * r > u is decided as log u < H0 - H1 in FP64, u in the open interval
+    (0, 1); a non-finite H1 is a rejected, divergent proposal (Sec. 4.3
+    reports infinite gradients in full-batch runs);
+  * fixed step size, no jitter; M = I unless a diagonal inverse mass is given.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import philox
+
+
+def kinetic(p, inv_mass=None) -> float:
+    p = np.asarray(p, dtype=np.float64)
+    if inv_mass is None:
+        return 0.5 * float(np.dot(p, p))
+    return 0.5 * float(np.dot(p * inv_mass, p))
+
+
+def leapfrog(potential_and_grad, theta, p, eps, L, inv_mass=None, start=None):
+    """L kick-drift-kick steps of Hamilton's equations dtheta/dt = M^-1 p,
+    dp/dt = -grad U.  Consecutive half kicks are merged, so there are exactly
+    L gradient evaluations after the starting one.
+
+    ``start`` = (U, g) at ``theta`` if already known.
+    Returns (theta_L, p_L, U_L, g_L)."""
+    theta = np.array(theta, dtype=np.float64)
+    p = np.array(p, dtype=np.float64)
+    minv = 1.0 if inv_mass is None else np.asarray(inv_mass, dtype=np.float64)
+    U, g = potential_and_grad(theta) if start is None else start
+    p = p - 0.5 * eps * g
+    for t in range(1, L + 1):
+        theta = theta + eps * minv * p
+        U, g = potential_and_grad(theta)
+        p = p - (eps if t < L else 0.5 * eps) * g
+    return theta, p, U, g
+
+
+def hamiltonian(U, p, inv_mass=None) -> float:
+    return float(U) + kinetic(p, inv_mass)
+
+
+def metropolis_accept(H0, H1, u) -> bool:
+    """Accept iff exp(-H1)/exp(-H0) > u, taken in log space; non-finite H1 rejects."""
+    if not math.isfinite(H1):
+        return False
+    return math.log(u) < H0 - H1
+
+
+def momentum(seed, chain, iteration, n, inv_mass=None):
+    """p ~ N(0, M) for the refresh of (chain, iteration) from the Philox stream."""
+    z = philox.normals(seed, chain, iteration, n)
+    if inv_mass is None:
+        return z
+    return z / np.sqrt(np.asarray(inv_mass, dtype=np.float64))
+
+
+def transition(potential_and_grad, theta, U, g, p, eps, L, u, inv_mass=None):
+    """One iteration of the loop of Algorithm 2 from state (theta, U, g) with
+    momentum p and uniform u.  Returns the next state and a stats dict."""
+    H0 = hamiltonian(U, p, inv_mass)
+    th1, p1, U1, g1 = leapfrog(potential_and_grad, theta, p, eps, L, inv_mass, start=(U, g))
+    H1 = hamiltonian(U1, p1, inv_mass)
+    acc = metropolis_accept(H0, H1, u)
+    stats = {"H0": H0, "H1": H1, "log_u": math.log(u), "accepted": acc,
+             "divergent": not math.isfinite(H1)}
+    if acc:
+        return th1, U1, g1, stats
+    return np.array(theta, dtype=np.float64), U, g, stats
+
+
+def sample_chain(potential_and_grad, theta_init, eps, L, n, seed, chain,
+                 inv_mass=None, start_iter=0):
+    """n iterations of Algorithm 2 for one chain.  Momentum and uniform come
+    from the Philox streams keyed by (seed, chain) at iteration
+    start_iter + i.  Returns (samples [n, n_s], list of stats)."""
+    theta = np.array(theta_init, dtype=np.float64)
+    U, g = potential_and_grad(theta)
+    out = np.empty((n, theta.size))
+    stats = []
+    for i in range(n):
+        it = start_iter + i
+        p = momentum(seed, chain, it, theta.size, inv_mass)
+        u = philox.metropolis_uniform(seed, chain, it)
+        theta, U, g, st = transition(potential_and_grad, theta, U, g, p, eps, L, u, inv_mass)
+        out[i] = theta
+        stats.append(st)
+    return out, stats
