@@ -1,0 +1,226 @@
+/*
+ * hmc.h - C ABI of the masked full-batch HMC engine (gfx950 / MI355X).
+ *
+ * The engine draws samples of the selected parameter subset Theta_s of a
+ * network while every other parameter stays at a given fixed value: the
+ * conditional posterior P(Theta_s | D, Theta_~s) of Sec. 3.2 of the paper,
+ * sampled by the HMC loop of Algorithm 2 (momentum refresh, leapfrog
+ * integration of Hamilton's equations of Sec. 2.2, Metropolis-Hastings
+ * step).  Each leapfrog step evaluates the network and its adjoint over the
+ * whole training set (full batch) and the gradient of
+ *
+ *     U(Theta_s) = sum over rows and outputs of (F - y)^2 / (2 lik_sd^2)
+ *                + sum over selected i of theta_i^2 / (2 prior_sd^2)
+ *
+ * with respect to the selected entries only (Gaussian prior and likelihood,
+ * App. C; additive constants dropped).  Kinetic energy is p^T M^-1 p / 2
+ * with a diagonal M (identity by default); the Hamiltonian, the likelihood
+ * sum and the Metropolis test are evaluated in FP64.
+ *
+ * Conventions
+ *  - Every function returns an hmc_status; a negative value is an error and
+ *    hmc_last_error() describes it.  Nothing aborts or throws across the ABI.
+ *  - All arguments are validated on the host before any device work, so an
+ *    HMC_EINVAL return leaves the engine state unchanged.
+ *  - The caller owns every input array; hmc_init copies what it needs, so the
+ *    inputs may be freed when it returns.  The library owns its device
+ *    buffers until hmc_destroy().
+ *  - Arrays documented "host or device" may be host memory or device memory
+ *    of the engine's GPU; the library copies with the unified-address copy.
+ *  - The "state type" of an engine is double for HMC_FP64 and float for
+ *    HMC_FP32 and HMC_BF16; positions, momenta and gradients cross the ABI in
+ *    that type, in the CSR order of the mask (chain by chain).
+ *  - Work is queued on the engine's stream.  Functions that return host
+ *    results (stats, energies, copies to host) synchronise that stream.
+ *  - A divergent (non-finite) trajectory is not an error: its proposal is
+ *    rejected and reported with divergent = 1 (Sec. 4.3 reports infinite
+ *    gradients in full-batch runs).
+ *  - One engine must not be used from two threads at once; separate engines
+ *    are independent.
+ */
+#ifndef HMC_H
+#define HMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmc_ctx hmc_ctx;
+
+typedef enum {
+    HMC_OK = 0,
+    HMC_EINVAL = -1,        /* invalid argument; state unchanged              */
+    HMC_ENOMEM = -2,        /* host or device allocation failed               */
+    HMC_EDEVICE = -3,       /* HIP runtime error (message in hmc_last_error)  */
+    HMC_ESTATE = -4,        /* call not valid in the engine's current state   */
+    HMC_EUNSUPPORTED = -5   /* a shape or option this build does not support  */
+} hmc_status;
+
+/* Number format of the layer products.  FP64: everything in double.
+ * FP32: products and states in float, energies in double.  BF16: products
+ * take bfloat16 operands with float accumulation, states in float, energies
+ * in double. */
+typedef enum { HMC_FP64 = 0, HMC_FP32 = 1, HMC_BF16 = 2 } hmc_precision;
+
+/* Network family (Sec. 2 and App. A).  An MLP is one fully connected tower;
+ * a DeepONet has a branch tower over input-function samples and a trunk
+ * tower over query coordinates, combined by a dot product plus a scalar
+ * bias b0.  Every layer is followed by tanh except the last of each tower. */
+typedef enum { HMC_MLP = 0, HMC_DEEPONET = 1 } hmc_net_kind;
+
+/* The network and the distribution.
+ * widths_a: MLP widths [d_in, hidden..., d_out] or branch widths [m, ..., p].
+ * widths_b: trunk widths [d_y, ..., p] for a DeepONet, else ignored.
+ * theta0: the full flat parameter vector (n_params doubles).  Order: tower by
+ *   tower (branch, then trunk, then b0), layer by layer, W[out][in]
+ *   row-major then b[out].  Entries outside the mask stay at these values
+ *   (Algorithm 2 fixes them at the VI means); selected entries start here
+ *   unless hmc_mask_desc.theta_init is given.
+ * inv_mass_diag: NULL for M = I, else n_params positive diagonal entries of
+ *   M^-1 (only the selected ones are used).
+ * Limits: 2..9 widths per tower, each width 1..4096. */
+typedef struct {
+    int32_t kind;
+    int32_t n_widths_a;
+    const int32_t* widths_a;
+    int32_t n_widths_b;
+    const int32_t* widths_b;
+    const double* theta0;
+    int64_t n_params;
+    double prior_sd;
+    double lik_sd;
+    int32_t precision;
+    const double* inv_mass_diag;
+} hmc_net_desc;
+
+/* The selected subset Theta_s of each chain (Sec. 3.2), as CSR over chains.
+ * offs[n_chains + 1] with offs[0] = 0; idx[offs[C]] flat indices, strictly
+ * increasing within each chain, in [0, n_params); every chain selects at
+ * least one entry.  Chains may select different subsets of different sizes.
+ * theta_init: NULL (start from theta0[idx]) or offs[C] starting values. */
+typedef struct {
+    int32_t n_chains;
+    const int64_t* offs;
+    const int64_t* idx;
+    const double* theta_init;
+} hmc_mask_desc;
+
+/* Training data D, host memory, row-major doubles.
+ * MLP: x[n_rows][d_in], y[n_rows][d_out].
+ * DeepONet: u[n_u][m] (branch inputs), yq[n_q][d_y] (trunk inputs, shared
+ * by every function), v[n_u][n_q] (targets). */
+typedef struct {
+    const double* x;
+    const double* y;
+    int64_t n_rows;
+    const double* u;
+    const double* yq;
+    const double* v;
+    int64_t n_u;
+    int64_t n_q;
+} hmc_data_desc;
+
+/* Outcome of one trajectory of one chain. */
+typedef struct {
+    double H0;          /* U(theta) + K(p) at the start                      */
+    double H1;          /* U(theta*) + K(p*) at the end of the trajectory    */
+    double log_u;       /* log of the Metropolis uniform                     */
+    int32_t accepted;   /* 1 if log_u < H0 - H1                              */
+    int32_t divergent;  /* 1 if H1 was not finite (proposal rejected)        */
+} hmc_traj_stat;
+
+typedef struct {
+    int64_t n_params;
+    int64_t nnz;              /* offs[n_chains]                              */
+    int32_t n_chains;
+    int32_t precision;
+    int32_t kind;
+    int32_t rows_per_tile_a;  /* rows of the MLP / branch tiles              */
+    int32_t rows_per_tile_b;  /* rows of the trunk tiles (DeepONet)          */
+    int32_t tiles_a;
+    int32_t tiles_b;
+    int64_t device_bytes;     /* device memory held by the engine            */
+} hmc_info_t;
+
+/* Creates an engine: validates, uploads data and parameters, and evaluates
+ * U and its gradient at the starting point of every chain.
+ * seed keys the Philox4x64-10 streams of the momentum refresh and of the
+ * Metropolis uniforms (key = (seed, chain), counter = (iteration, stream,
+ * block, 0)).  hip_stream: a hipStream_t to queue work on, or NULL for a
+ * stream owned by the engine.  *out is NULL on failure. */
+hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask,
+                    const hmc_data_desc* data, uint64_t seed, void* hip_stream);
+
+/* One iteration of the loop of Algorithm 2 for the listed chains: draw
+ * p ~ N(0, M), integrate L leapfrog steps of size eps[i] for chain
+ * chain_ids[i] (kick-drift-kick, exactly L gradient evaluations), then
+ * accept or reject.  chain_ids NULL means chains 0..n_chains-1.
+ * eps: host, n_chains positive finite values.  stats: host [n_chains] or
+ * NULL (no synchronisation then). */
+hmc_status hmc_leapfrog(hmc_ctx* ctx, int32_t n_chains, const int32_t* chain_ids,
+                        const double* eps, int32_t L, hmc_traj_stat* stats);
+
+/* n iterations of Algorithm 2 for every chain, each chain with its own step
+ * size eps[c] (host, C values) and a common L.  After iteration i the
+ * positions of all chains are written to samples + i * nnz (state type, host
+ * or device, or NULL).  stats: host [n][C] or NULL. */
+hmc_status hmc_sample(hmc_ctx* ctx, int64_t n, const double* eps, int32_t L,
+                      void* samples, hmc_traj_stat* stats);
+
+/* U (host, [C]) and the gradient of U with respect to the selected entries
+ * (state type, host or device, [nnz]) at the current positions. */
+hmc_status hmc_grad(hmc_ctx* ctx, double* U, void* g);
+
+/* A trajectory without Metropolis step and without changing the engine
+ * state: starting from the current positions with momentum p0 (state type,
+ * host or device, [nnz]), run L leapfrog steps of size eps[c] (host, [C]) and
+ * return the end point theta_out, p_out ([nnz], host or device, may be NULL)
+ * and H0, H1 (host, [C], may be NULL). */
+hmc_status hmc_trajectory(hmc_ctx* ctx, const void* p0, const double* eps, int32_t L,
+                          void* theta_out, void* p_out, double* H0, double* H1);
+
+/* The momentum that the refresh of iteration `iteration` draws, for every
+ * chain (state type, host or device, [nnz]). */
+hmc_status hmc_momentum(hmc_ctx* ctx, uint64_t iteration, void* p_out);
+
+/* Current positions (state type, host or device, [nnz], may be NULL), U
+ * (host [C] or NULL) and per-chain iteration counters (host [C] or NULL). */
+hmc_status hmc_get_state(hmc_ctx* ctx, void* theta_s, double* U, uint64_t* iteration);
+
+/* Sets the positions (state type, host or device, [nnz]) and iteration
+ * counters (host [C], or NULL to keep them), and re-evaluates U and the
+ * gradient.  Together with hmc_get_state this checkpoints and resumes a run:
+ * the counter-based streams make the continuation identical. */
+hmc_status hmc_set_state(hmc_ctx* ctx, const void* theta_s, const uint64_t* iteration);
+
+/* Accepted and divergent trajectory counts per chain since hmc_init (host,
+ * [C] each, either may be NULL). */
+hmc_status hmc_counters(hmc_ctx* ctx, int64_t* accepted, int64_t* divergent);
+
+hmc_status hmc_get_info(const hmc_ctx* ctx, hmc_info_t* info);
+
+/* Measurement hook: launches each gradient-evaluation kernel `reps` times
+ * back to back on the engine's stream between two HIP events and writes the
+ * mean milliseconds per launch to ms[0..3]:
+ *   ms[0] fused forward/adjoint/masked-gradient kernel (MLP or branch),
+ *   ms[1] trunk forward (DeepONet, else 0), ms[2] trunk adjoint (DeepONet,
+ *   else 0), ms[3] reduction of the per-tile gradient partials.
+ * The engine state is unchanged. */
+hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
+
+/* Waits for queued work and reports deferred device errors. */
+hmc_status hmc_sync(hmc_ctx* ctx);
+
+/* NUL-terminated description of the last error on ctx (ctx may be NULL for
+ * errors of a failed hmc_init); valid until the next call on ctx. */
+const char* hmc_last_error(const hmc_ctx* ctx);
+
+void hmc_destroy(hmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_H */

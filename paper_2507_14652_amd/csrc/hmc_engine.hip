@@ -1,0 +1,868 @@
+// Host engine behind the C ABI of include/hmc.h: validation, device layout,
+// launch sequencing of the leapfrog trajectory, graph capture of whole
+// trajectories, and the measurement hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hmc.h"
+#include "hmc_launch.hpp"
+#include "hmc_plan.hpp"
+
+namespace {
+
+thread_local std::string g_init_error;
+
+size_t g_lds_cap = 160 * 1024;   // LDS per workgroup on gfx950; replaced by the device's value
+
+int pad_of(int prec) { return prec == HMC_BF16 ? 32 : 16; }
+int lpad_of(int prec) { return prec == HMC_BF16 ? 8 : 4; }
+size_t tsize_of(int prec) { return prec == HMC_FP64 ? 8 : prec == HMC_FP32 ? 4 : 2; }   // product type
+size_t asize_of(int prec) { return prec == HMC_FP64 ? 8 : 4; }                          // accumulator / bias type
+size_t ssize_of(int prec) { return prec == HMC_FP64 ? 8 : 4; }                          // state type
+int roundup(int x, int m) { return (x + m - 1) / m * m; }
+long long roundupl(long long x, long long m) { return (x + m - 1) / m * m; }
+
+uint16_t to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;   // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);                                             // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+// Stores v in the product type at index i of a byte buffer.
+void put_t(std::vector<unsigned char>& buf, int prec, size_t i, double v) {
+    if (prec == HMC_FP64) { std::memcpy(&buf[i * 8], &v, 8); return; }
+    const float f = (float)v;
+    if (prec == HMC_FP32) { std::memcpy(&buf[i * 4], &f, 4); return; }
+    const uint16_t b = to_bf16_bits(f);
+    std::memcpy(&buf[i * 2], &b, 2);
+}
+void put_a(std::vector<unsigned char>& buf, int prec, size_t i, double v) {
+    if (prec == HMC_FP64) { std::memcpy(&buf[i * 8], &v, 8); return; }
+    const float f = (float)v;
+    std::memcpy(&buf[i * 4], &f, 4);
+}
+
+struct TowerHost {
+    std::vector<int> w;
+    long long flat0 = 0;                 // flat index of the tower's first parameter
+    std::vector<long long> lstart;       // flat index of each layer's first parameter
+};
+
+}  // namespace
+
+struct hmc_ctx {
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+
+    int kind = 0, prec = 0;
+    TowerHost A, B;
+    long long P = 0;
+    double prior_sd = 1, lik_sd = 1;
+    int C = 0;
+    long long nnz = 0;
+    std::vector<long long> offs;
+    int max_n = 0;
+    int Ra = 0, Rb = 0, tiles_a = 0, tiles_b = 0;
+    int grid_a = 0, grid_b = 0;
+    size_t lds_a = 0, lds_b = 0;
+    GradArgs ga{};
+    StateArgs sa{};
+    std::vector<void*> allocs;
+    long long dev_bytes = 0;
+    std::vector<int> active_h;
+    void* pin = nullptr;          // device [nnz] state type: injected momentum
+    void* ptmp = nullptr;         // device [nnz] state type: momentum preview
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_L = -1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    hmc_status fail(hmc_status s, const std::string& m) { err = m; return s; }
+    hmc_status hip(hipError_t e, const char* what) {
+        if (e == hipSuccess) return HMC_OK;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return HMC_EDEVICE;
+    }
+    void* dalloc(size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        if (hipMemset(p, 0, bytes) != hipSuccess) { (void)hipFree(p); return nullptr; }
+        allocs.push_back(p);
+        dev_bytes += (long long)bytes;
+        return p;
+    }
+};
+
+#define HMC_TRY(expr)                          \
+    do {                                       \
+        hmc_status s__ = (expr);               \
+        if (s__ != HMC_OK) return s__;         \
+    } while (0)
+#define HMC_HIP(x, call) HMC_TRY((x)->hip((call), #call))
+
+namespace {
+
+// ----------------------------------------------------------------- validation
+
+hmc_status check_tower(const int32_t* w, int32_t n, const char* name, std::string& err) {
+    if (!w) { err = std::string(name) + " is NULL"; return HMC_EINVAL; }
+    if (n < 2 || n > HMC_MAXL + 1) {
+        err = std::string(name) + ": need 2.." + std::to_string(HMC_MAXL + 1) + " widths";
+        return HMC_EINVAL;
+    }
+    for (int i = 0; i < n; ++i)
+        if (w[i] < 1 || w[i] > 4096) { err = std::string(name) + ": widths must be in 1..4096"; return HMC_EINVAL; }
+    return HMC_OK;
+}
+
+long long tower_count(const std::vector<int>& w) {
+    long long n = 0;
+    for (size_t i = 0; i + 1 < w.size(); ++i) n += (long long)w[i] * w[i + 1] + w[i + 1];
+    return n;
+}
+
+hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                    std::string& err) {
+    if (!net || !mask || !data) { err = "net, mask and data must be non-NULL"; return HMC_EINVAL; }
+    if (net->kind != HMC_MLP && net->kind != HMC_DEEPONET) { err = "unknown network kind"; return HMC_EINVAL; }
+    if (net->precision < HMC_FP64 || net->precision > HMC_BF16) { err = "unknown precision"; return HMC_EINVAL; }
+    HMC_TRY(check_tower(net->widths_a, net->n_widths_a, "widths_a", err));
+    std::vector<int> wa(net->widths_a, net->widths_a + net->n_widths_a), wb;
+    long long P = tower_count(wa);
+    if (net->kind == HMC_DEEPONET) {
+        HMC_TRY(check_tower(net->widths_b, net->n_widths_b, "widths_b", err));
+        wb.assign(net->widths_b, net->widths_b + net->n_widths_b);
+        if (wa.back() != wb.back()) { err = "branch and trunk output widths differ"; return HMC_EINVAL; }
+        P += tower_count(wb) + 1;
+    }
+    if (net->n_params != P) {
+        err = "n_params = " + std::to_string(net->n_params) + " but the network has " + std::to_string(P);
+        return HMC_EINVAL;
+    }
+    if (!net->theta0) { err = "theta0 is NULL"; return HMC_EINVAL; }
+    if (!(net->prior_sd > 0) || !std::isfinite(net->prior_sd)) { err = "prior_sd must be positive and finite"; return HMC_EINVAL; }
+    if (!(net->lik_sd > 0) || !std::isfinite(net->lik_sd)) { err = "lik_sd must be positive and finite"; return HMC_EINVAL; }
+    if (net->inv_mass_diag)
+        for (long long i = 0; i < P; ++i)
+            if (!(net->inv_mass_diag[i] > 0) || !std::isfinite(net->inv_mass_diag[i])) {
+                err = "inv_mass_diag entries must be positive and finite";
+                return HMC_EINVAL;
+            }
+    if (mask->n_chains < 1 || mask->n_chains > 65535) { err = "n_chains must be in 1..65535"; return HMC_EINVAL; }
+    if (!mask->offs || !mask->idx) { err = "mask offs and idx must be non-NULL"; return HMC_EINVAL; }
+    if (mask->offs[0] != 0) { err = "mask offs[0] must be 0"; return HMC_EINVAL; }
+    for (int c = 0; c < mask->n_chains; ++c) {
+        const long long a = mask->offs[c], b = mask->offs[c + 1];
+        if (b <= a) { err = "chain " + std::to_string(c) + " selects no entry"; return HMC_EINVAL; }
+        if (b - a > (1ll << 30)) { err = "too many entries in one chain"; return HMC_EINVAL; }
+        for (long long k = a; k < b; ++k) {
+            const long long f = mask->idx[k];
+            if (f < 0 || f >= P) { err = "mask index out of range in chain " + std::to_string(c); return HMC_EINVAL; }
+            if (k > a && f <= mask->idx[k - 1]) {
+                err = "mask indices must be strictly increasing within chain " + std::to_string(c);
+                return HMC_EINVAL;
+            }
+        }
+    }
+    if (net->kind == HMC_MLP) {
+        if (!data->x || !data->y) { err = "MLP data needs x and y"; return HMC_EINVAL; }
+        if (data->n_rows < 1 || data->n_rows > (1ll << 30)) { err = "n_rows out of range"; return HMC_EINVAL; }
+    } else {
+        if (!data->u || !data->yq || !data->v) { err = "DeepONet data needs u, yq and v"; return HMC_EINVAL; }
+        if (data->n_u < 1 || data->n_q < 1 || data->n_u > (1ll << 24) || data->n_q > (1ll << 24)) {
+            err = "n_u and n_q out of range";
+            return HMC_EINVAL;
+        }
+    }
+    return HMC_OK;
+}
+
+// ----------------------------------------------------------------- planning
+
+size_t tower_lds(const std::vector<int>& w, int prec, int R) {
+    size_t e = 0;
+    for (int x : w) e += (size_t)R * (roundup(x, pad_of(prec)) + lpad_of(prec));
+    return e * tsize_of(prec);
+}
+
+void fill_plan(TowerPlan& tp, const std::vector<int>& w, int prec, int R) {
+    std::memset(&tp, 0, sizeof(tp));
+    tp.nl = (int)w.size() - 1;
+    int off = 0;
+    for (size_t l = 0; l < w.size(); ++l) {
+        tp.w[l] = w[l];
+        tp.wp[l] = roundup(w[l], pad_of(prec));
+        tp.ls[l] = tp.wp[l] + lpad_of(prec);
+        tp.lo[l] = off;
+        off += R * tp.ls[l];
+    }
+}
+
+// Largest row tile whose LDS footprint fits, shrunk while the grid would
+// leave most compute units idle.  HMC_ROWS_A / HMC_ROWS_B override it.
+int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, long long rows, int chains,
+              const char* env) {
+    if (const char* s = std::getenv(env)) {
+        const int r = std::atoi(s);
+        if ((r == 16 || r == 32 || r == 64) && tower_lds(w, prec, r) + extra_per_row * r + 64 <= g_lds_cap) return r;
+    }
+    int best = 0;
+    for (int R : {64, 32, 16})
+        if (tower_lds(w, prec, R) + extra_per_row * R + 64 <= g_lds_cap) { best = R; break; }
+    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 512 &&
+           tower_lds(w, prec, best / 2) + extra_per_row * (best / 2) + 64 <= g_lds_cap)
+        best /= 2;
+    return best;
+}
+
+hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
+    const int P = x->prec;
+    if (x->kind == HMC_MLP) {
+        HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, s));
+    } else {
+        HMC_HIP(x, hmc_launch_trunk_fwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, s));
+        HMC_HIP(x, hmc_launch_branch_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, s));
+        HMC_HIP(x, hmc_launch_trunk_bwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, s));
+    }
+    return HMC_OK;
+}
+
+int update_grid(const hmc_ctx* x) { return (x->max_n + 255) / 256; }
+
+// Gradient and U at the current positions (no kick).
+hmc_status launch_refresh(hmc_ctx* x, hipStream_t s) {
+    HMC_TRY(launch_grad(x, s));
+    HMC_HIP(x, hmc_launch_update(x->prec, x->sa, UPD_GRAD, update_grid(x), s));
+    HMC_HIP(x, hmc_launch_traj_end(x->prec, x->sa, END_ENERGY, s));
+    return HMC_OK;
+}
+
+// Leapfrog part of a trajectory: begin (refresh or injected momentum, first
+// half kick and drift), then L gradient evaluations each followed by a kick;
+// all but the last kick are full steps followed by a drift.
+hmc_status launch_leapfrog(hmc_ctx* x, const StateArgs& sa, int L, hipStream_t s) {
+    HMC_HIP(x, hmc_launch_traj_begin(x->prec, sa, s));
+    for (int t = 1; t <= L; ++t) {
+        HMC_TRY(launch_grad(x, s));
+        HMC_HIP(x, hmc_launch_update(x->prec, sa, t < L ? UPD_KICK_DRIFT : UPD_HALF_KICK, update_grid(x), s));
+    }
+    return HMC_OK;
+}
+
+hmc_status set_eps_active(hmc_ctx* x, const std::vector<double>& eps, const std::vector<int>& active) {
+    HMC_HIP(x, hipMemcpyAsync((void*)x->sa.eps, eps.data(), sizeof(double) * x->C, hipMemcpyHostToDevice, x->stream));
+    if (active != x->active_h) {
+        HMC_HIP(x, hipMemcpyAsync((void*)x->sa.active, active.data(), sizeof(int) * x->C, hipMemcpyHostToDevice,
+                                  x->stream));
+        x->active_h = active;
+    }
+    return HMC_OK;
+}
+
+hmc_status check_eps(hmc_ctx* x, const double* eps, int n, int L) {
+    if (!eps) return x->fail(HMC_EINVAL, "eps is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!(eps[i] > 0) || !std::isfinite(eps[i])) return x->fail(HMC_EINVAL, "eps must be positive and finite");
+    if (L < 1 || L > 1000000) return x->fail(HMC_EINVAL, "L must be in 1..1000000");
+    return HMC_OK;
+}
+
+hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                 uint64_t seed) {
+    const int prec = x->prec;
+    const size_t ts = tsize_of(prec), as = asize_of(prec), ss = ssize_of(prec);
+    const int pad = pad_of(prec);
+    int cap = 0;
+    HMC_HIP(x, hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, x->device));
+    if (cap > 0) g_lds_cap = (size_t)cap;
+    x->prior_sd = net->prior_sd;
+    x->lik_sd = net->lik_sd;
+    x->C = mask->n_chains;
+    x->offs.assign(mask->offs, mask->offs + x->C + 1);
+    x->nnz = x->offs[x->C];
+    for (int c = 0; c < x->C; ++c) x->max_n = std::max<int>(x->max_n, (int)(x->offs[c + 1] - x->offs[c]));
+    const int la = (int)x->A.w.size() - 1;
+    const int lb = x->kind == HMC_DEEPONET ? (int)x->B.w.size() - 1 : 0;
+
+    // Row tiles.
+    long long rows_a, rows_b = 0;
+    int nq_pad = 0;
+    if (x->kind == HMC_MLP) {
+        rows_a = data->n_rows;
+        x->Ra = pick_rows(x->A.w, prec, 0, rows_a, x->C, "HMC_ROWS_A");
+    } else {
+        rows_a = data->n_u;
+        rows_b = data->n_q;
+        nq_pad = roundup((int)rows_b, pad);
+        x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, rows_a, x->C, "HMC_ROWS_A");
+        x->Rb = pick_rows(x->B.w, prec, 0, rows_b, x->C, "HMC_ROWS_B");
+        if (!x->Rb) return x->fail(HMC_EUNSUPPORTED, "trunk tower does not fit in LDS");
+    }
+    if (!x->Ra) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS at 16 rows per tile");
+    x->tiles_a = (int)((rows_a + x->Ra - 1) / x->Ra);
+    x->tiles_b = x->kind == HMC_DEEPONET ? (int)((rows_b + x->Rb - 1) / x->Rb) : 0;
+    if ((long long)x->C * x->tiles_a > (1ll << 30) || (long long)x->C * x->tiles_b > (1ll << 30))
+        return x->fail(HMC_EUNSUPPORTED, "grid too large");
+    x->grid_a = roundup(x->C * x->tiles_a, 8);
+    x->grid_b = roundup(x->C * x->tiles_b, 8);
+
+    GradArgs& g = x->ga;
+    fill_plan(g.ta, x->A.w, prec, x->Ra);
+    g.ta.seg0 = 0;
+    if (x->kind == HMC_DEEPONET) {
+        fill_plan(g.tb, x->B.w, prec, x->Rb);
+        g.tb.seg0 = la;
+    }
+
+    // Per-chain weight and bias layout.
+    long long wofs = 0, bofs = 0;
+    auto lay = [&](TowerPlan& tp) {
+        for (int l = 0; l < tp.nl; ++l) {
+            const long long sz = (long long)tp.wp[l] * tp.wp[l + 1];
+            tp.wo[l] = wofs; wofs += sz;
+            tp.wto[l] = wofs; wofs += sz;
+            tp.bo[l] = bofs; bofs += tp.wp[l + 1];
+        }
+    };
+    lay(g.ta);
+    if (x->kind == HMC_DEEPONET) lay(g.tb);
+    g.b0_off = bofs;
+    bofs += 1;
+    g.wstride = roundupl(std::max(wofs, 1ll), 64);
+    g.bstride = roundupl(bofs, 64);
+
+    // Dense weights from theta0 (identical for every chain before the scatter).
+    std::vector<unsigned char> wh((size_t)g.wstride * ts, 0), bh((size_t)g.bstride * as, 0);
+    auto fill_tower = [&](const TowerPlan& tp, const TowerHost& th) {
+        for (int l = 0; l < tp.nl; ++l) {
+            const int in = tp.w[l], out = tp.w[l + 1];
+            const long long f0 = th.lstart[l];
+            for (int i = 0; i < out; ++i) {
+                for (int j = 0; j < in; ++j) {
+                    const double v = net->theta0[f0 + (long long)i * in + j];
+                    put_t(wh, prec, (size_t)(tp.wo[l] + (long long)i * tp.wp[l] + j), v);
+                    put_t(wh, prec, (size_t)(tp.wto[l] + (long long)j * tp.wp[l + 1] + i), v);
+                }
+                put_a(bh, prec, (size_t)(tp.bo[l] + i), net->theta0[f0 + (long long)out * in + i]);
+            }
+        }
+    };
+    fill_tower(g.ta, x->A);
+    if (x->kind == HMC_DEEPONET) {
+        fill_tower(g.tb, x->B);
+        put_a(bh, prec, (size_t)g.b0_off, net->theta0[x->P - 1]);
+    }
+    void* wd = x->dalloc((size_t)x->C * g.wstride * ts);
+    void* bd = x->dalloc((size_t)x->C * g.bstride * as);
+    if (!wd || !bd) return x->fail(HMC_ENOMEM, "device allocation of the weights failed");
+    for (int c = 0; c < x->C; ++c) {
+        HMC_HIP(x, hipMemcpy((char*)wd + (size_t)c * g.wstride * ts, wh.data(), wh.size(), hipMemcpyHostToDevice));
+        HMC_HIP(x, hipMemcpy((char*)bd + (size_t)c * g.bstride * as, bh.data(), bh.size(), hipMemcpyHostToDevice));
+    }
+    g.wbuf = wd;
+    g.bbuf = bd;
+
+    // Input rows, padded to whole tiles and padded widths, in the product type.
+    auto upload_rows = [&](const double* src, long long rows, int w, int wp, int R, int tiles) -> void* {
+        std::vector<unsigned char> h((size_t)tiles * R * wp * ts, 0);
+        for (long long r = 0; r < rows; ++r)
+            for (int j = 0; j < w; ++j) put_t(h, prec, (size_t)(r * wp + j), src[r * w + j]);
+        void* d = x->dalloc(h.size());
+        if (d && hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        return d;
+    };
+    double* tgt;
+    if (x->kind == HMC_MLP) {
+        g.xa = upload_rows(data->x, rows_a, x->A.w[0], g.ta.wp[0], x->Ra, x->tiles_a);
+        const int dout = x->A.w.back();
+        tgt = (double*)x->dalloc(sizeof(double) * rows_a * dout);
+        if (!g.xa || !tgt) return x->fail(HMC_ENOMEM, "device allocation of the data failed");
+        HMC_HIP(x, hipMemcpy(tgt, data->y, sizeof(double) * rows_a * dout, hipMemcpyHostToDevice));
+        g.d_out = dout;
+    } else {
+        g.xa = upload_rows(data->u, rows_a, x->A.w[0], g.ta.wp[0], x->Ra, x->tiles_a);
+        g.xb = upload_rows(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb, x->tiles_b);
+        tgt = (double*)x->dalloc(sizeof(double) * rows_a * rows_b);
+        if (!g.xa || !g.xb || !tgt) return x->fail(HMC_ENOMEM, "device allocation of the data failed");
+        HMC_HIP(x, hipMemcpy(tgt, data->v, sizeof(double) * rows_a * rows_b, hipMemcpyHostToDevice));
+        const int pp = g.ta.wp[la];
+        g.nq = (int)rows_b;
+        g.nq_pad = nq_pad;
+        g.nq_rows = std::max(nq_pad, x->tiles_b * x->Rb);
+        g.nu_cols = roundup(x->tiles_a * x->Ra, 32);
+        g.tm_stride = (long long)g.nq_rows * pp;
+        g.bt_stride = (long long)pp * g.nu_cols;
+        g.dgt_stride = (long long)g.nq_rows * g.nu_cols;
+        g.tm = x->dalloc((size_t)x->C * g.tm_stride * ts);
+        g.tt = x->dalloc((size_t)x->C * g.tm_stride * ts);
+        g.btr = x->dalloc((size_t)x->C * g.bt_stride * ts);
+        g.dgt = x->dalloc((size_t)x->C * g.dgt_stride * ts);
+        if (!g.tm || !g.tt || !g.btr || !g.dgt) return x->fail(HMC_ENOMEM, "device allocation of the exchange buffers failed");
+    }
+    g.target = tgt;
+    g.n_rows_a = (int)rows_a;
+    g.n_rows_b = (int)rows_b;
+    g.tiles_a = x->tiles_a;
+    g.tiles_b = x->tiles_b;
+    g.n_chains = x->C;
+    g.inv_lik_var = 1.0 / (net->lik_sd * net->lik_sd);
+
+    // LDS: activation slabs [+ output-adjoint slab] + reduction scratch.
+    x->lds_a = tower_lds(x->A.w, prec, x->Ra);
+    if (x->kind == HMC_DEEPONET) {
+        g.dg_off = (int)(x->lds_a / ts);
+        g.dg_ld = nq_pad + lpad_of(prec);
+        x->lds_a += (size_t)x->Ra * g.dg_ld * ts;
+    }
+    x->lds_a = (x->lds_a + 15) / 16 * 16;
+    g.red_off = (int)x->lds_a;
+    x->lds_a += 64;
+    // The per-kernel limit is set to the device capacity (not this engine's
+    // size) so that engines of different shapes in one process coexist.
+    HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
+    if (x->kind == HMC_DEEPONET) {
+        x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
+        HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
+    }
+
+    // Mask tables: entry codes, per-layer segments, scatter destinations.
+    const int nseg = la + lb + 2;
+    std::vector<int> code((size_t)x->nnz), dst((size_t)2 * x->nnz), seg((size_t)x->C * nseg);
+    std::vector<long long> lstart;   // flat start of every layer, then b0
+    std::vector<const TowerPlan*> lplan;
+    std::vector<int> lidx;
+    for (int l = 0; l < la; ++l) { lstart.push_back(x->A.lstart[l]); lplan.push_back(&g.ta); lidx.push_back(l); }
+    for (int l = 0; l < lb; ++l) { lstart.push_back(x->B.lstart[l]); lplan.push_back(&g.tb); lidx.push_back(l); }
+    const long long b0_flat = x->kind == HMC_DEEPONET ? x->P - 1 : x->P;
+    lstart.push_back(b0_flat);
+    for (int c = 0; c < x->C; ++c) {
+        const long long o = x->offs[c], n = x->offs[c + 1] - o;
+        const int64_t* id = mask->idx + o;
+        for (int s = 0; s < la + lb + 1; ++s)
+            seg[(size_t)c * nseg + s] = (int)(std::lower_bound(id, id + n, (int64_t)lstart[s]) - id);
+        seg[(size_t)c * nseg + nseg - 1] = (int)n;
+        int layer = 0;
+        for (long long k = 0; k < n; ++k) {
+            const long long f = id[k];
+            while (layer < la + lb && f >= lstart[layer + 1]) ++layer;
+            const size_t e = (size_t)(o + k);
+            if (layer == la + lb) {   // b0
+                code[e] = 0xFFFF;
+                dst[2 * e] = -(int)g.b0_off - 1;
+                dst[2 * e + 1] = -1;
+                continue;
+            }
+            const TowerPlan& tp = *lplan[layer];
+            const int l = lidx[layer];
+            const int in = tp.w[l], out = tp.w[l + 1];
+            const long long off = f - lstart[layer];
+            if (off < (long long)in * out) {
+                const int i = (int)(off / in), j = (int)(off % in);
+                code[e] = (i << 16) | j;
+                dst[2 * e] = (int)(tp.wo[l] + (long long)i * tp.wp[l] + j);
+                dst[2 * e + 1] = (int)(tp.wto[l] + (long long)j * tp.wp[l + 1] + i);
+            } else {
+                const int i = (int)(off - (long long)in * out);
+                code[e] = (i << 16) | 0xFFFF;
+                dst[2 * e] = -(int)(tp.bo[l] + i) - 1;
+                dst[2 * e + 1] = -1;
+            }
+        }
+    }
+    long long* offs_d = (long long*)x->dalloc(sizeof(long long) * (x->C + 1));
+    int* code_d = (int*)x->dalloc(sizeof(int) * x->nnz);
+    int* dst_d = (int*)x->dalloc(sizeof(int) * 2 * x->nnz);
+    int* seg_d = (int*)x->dalloc(sizeof(int) * seg.size());
+    int* act_d = (int*)x->dalloc(sizeof(int) * x->C);
+    if (!offs_d || !code_d || !dst_d || !seg_d || !act_d) return x->fail(HMC_ENOMEM, "device allocation of the mask tables failed");
+    HMC_HIP(x, hipMemcpy(offs_d, x->offs.data(), sizeof(long long) * (x->C + 1), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(code_d, code.data(), sizeof(int) * x->nnz, hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(dst_d, dst.data(), sizeof(int) * 2 * x->nnz, hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(seg_d, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice));
+    x->active_h.assign(x->C, 1);
+    HMC_HIP(x, hipMemcpy(act_d, x->active_h.data(), sizeof(int) * x->C, hipMemcpyHostToDevice));
+    g.active = act_d;
+    g.offs = offs_d;
+    g.ecode = code_d;
+    g.seg = seg_d;
+    g.nseg = nseg;
+    g.tmax = std::max(x->tiles_a, x->tiles_b);
+    g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
+    g.ulik = (double*)x->dalloc(sizeof(double) * x->C * x->tiles_a);
+    if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
+
+    // Chain state.
+    StateArgs& s = x->sa;
+    s.n_chains = x->C;
+    s.active = act_d;
+    s.offs = offs_d;
+    s.seg = seg_d;
+    s.nseg = nseg;
+    s.seg_trunk_lo = la;
+    s.seg_trunk_hi = la + lb;
+    s.tiles_a = x->tiles_a;
+    s.tiles_b = x->tiles_b;
+    s.tmax = g.tmax;
+    s.part = g.part;
+    s.ulik = g.ulik;
+    s.dst = dst_d;
+    s.wbuf = wd;
+    s.wstride = g.wstride;
+    s.bbuf = bd;
+    s.bstride = g.bstride;
+    s.inv_prior_var = 1.0 / (net->prior_sd * net->prior_sd);
+    s.seed = seed;
+    const size_t sb = (size_t)x->nnz * ss;
+    s.theta = x->dalloc(sb);
+    s.mom = x->dalloc(sb);
+    s.grad = x->dalloc(sb);
+    s.theta_save = x->dalloc(sb);
+    s.grad_save = x->dalloc(sb);
+    x->pin = x->dalloc(sb);
+    x->ptmp = x->dalloc(sb);
+    s.eps = (const double*)x->dalloc(sizeof(double) * x->C);
+    s.U = (double*)x->dalloc(sizeof(double) * x->C);
+    s.U_save = (double*)x->dalloc(sizeof(double) * x->C);
+    s.H0 = (double*)x->dalloc(sizeof(double) * x->C);
+    s.H1 = (double*)x->dalloc(sizeof(double) * x->C);
+    s.iter = (unsigned long long*)x->dalloc(sizeof(unsigned long long) * x->C);
+    s.stats = x->dalloc(sizeof(hmc_traj_stat) * x->C);
+    s.n_acc = (long long*)x->dalloc(sizeof(long long) * x->C);
+    s.n_div = (long long*)x->dalloc(sizeof(long long) * x->C);
+    if (!s.theta || !s.mom || !s.grad || !s.theta_save || !s.grad_save || !x->pin || !x->ptmp || !s.eps || !s.U ||
+        !s.U_save || !s.H0 || !s.H1 || !s.iter || !s.stats || !s.n_acc || !s.n_div)
+        return x->fail(HMC_ENOMEM, "device allocation of the chain state failed");
+    std::vector<unsigned char> th(sb);
+    for (long long e = 0; e < x->nnz; ++e) {
+        const double v = mask->theta_init ? mask->theta_init[e] : net->theta0[mask->idx[e]];
+        if (prec == HMC_FP64) std::memcpy(&th[e * 8], &v, 8);
+        else { const float f = (float)v; std::memcpy(&th[e * 4], &f, 4); }
+    }
+    HMC_HIP(x, hipMemcpy(s.theta, th.data(), sb, hipMemcpyHostToDevice));
+    if (net->inv_mass_diag) {
+        void* m = x->dalloc(sb);
+        if (!m) return x->fail(HMC_ENOMEM, "device allocation of the mass matrix failed");
+        for (long long e = 0; e < x->nnz; ++e) {
+            const double v = net->inv_mass_diag[mask->idx[e]];
+            if (prec == HMC_FP64) std::memcpy(&th[e * 8], &v, 8);
+            else { const float f = (float)v; std::memcpy(&th[e * 4], &f, 4); }
+        }
+        HMC_HIP(x, hipMemcpy(m, th.data(), sb, hipMemcpyHostToDevice));
+        s.minv = m;
+    }
+    HMC_HIP(x, hipEventCreate(&x->ev0));
+    HMC_HIP(x, hipEventCreate(&x->ev1));
+    HMC_HIP(x, hipStreamCreateWithFlags(&x->cap_stream, hipStreamNonBlocking));
+
+    // Scatter the starting positions and evaluate U and the gradient there.
+    HMC_HIP(x, hmc_launch_scatter_all(prec, s, x->stream));
+    HMC_TRY(launch_refresh(x, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+void release(hmc_ctx* x) {
+    if (x->stream) (void)hipStreamSynchronize(x->stream);
+    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    for (void* p : x->allocs) (void)hipFree(p);
+    x->allocs.clear();
+    if (x->ev0) (void)hipEventDestroy(x->ev0);
+    if (x->ev1) (void)hipEventDestroy(x->ev1);
+    if (x->cap_stream) (void)hipStreamDestroy(x->cap_stream);
+    if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
+}
+
+// Graph of one full iteration of Algorithm 2 for every chain, captured once
+// per L.  Step sizes, active flags and iteration counters live in device
+// memory, so replays need no re-capture.
+hmc_status trajectory_graph(hmc_ctx* x, int L) {
+    if (x->gexec && x->graph_L == L) return HMC_OK;
+    if (x->gexec) { (void)hipGraphExecDestroy(x->gexec); x->gexec = nullptr; }
+    if (x->graph) { (void)hipGraphDestroy(x->graph); x->graph = nullptr; }
+    HMC_HIP(x, hipStreamBeginCapture(x->cap_stream, hipStreamCaptureModeThreadLocal));
+    hmc_status st = launch_leapfrog(x, x->sa, L, x->cap_stream);
+    if (st == HMC_OK) {
+        hipError_t e = hmc_launch_traj_end(x->prec, x->sa, END_METROPOLIS, x->cap_stream);
+        if (e != hipSuccess) st = x->hip(e, "traj_end");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(x->cap_stream, &g);
+    if (st != HMC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    HMC_HIP(x, ec);
+    x->graph = g;
+    HMC_HIP(x, hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0));
+    x->graph_L = L;
+    return HMC_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                    uint64_t seed, void* hip_stream) {
+    g_init_error.clear();
+    if (!out) { g_init_error = "out is NULL"; return HMC_EINVAL; }
+    *out = nullptr;
+    std::string err;
+    hmc_status st = validate(net, mask, data, err);
+    if (st != HMC_OK) { g_init_error = err; return st; }
+    hmc_ctx* x = new (std::nothrow) hmc_ctx();
+    if (!x) { g_init_error = "out of host memory"; return HMC_ENOMEM; }
+    x->kind = net->kind;
+    x->prec = net->precision;
+    x->A.w.assign(net->widths_a, net->widths_a + net->n_widths_a);
+    x->P = net->n_params;
+    long long f = 0;
+    for (size_t l = 0; l + 1 < x->A.w.size(); ++l) {
+        x->A.lstart.push_back(f);
+        f += (long long)x->A.w[l] * x->A.w[l + 1] + x->A.w[l + 1];
+    }
+    if (x->kind == HMC_DEEPONET) {
+        x->B.w.assign(net->widths_b, net->widths_b + net->n_widths_b);
+        x->B.flat0 = f;
+        for (size_t l = 0; l + 1 < x->B.w.size(); ++l) {
+            x->B.lstart.push_back(f);
+            f += (long long)x->B.w[l] * x->B.w[l + 1] + x->B.w[l + 1];
+        }
+    }
+    hipError_t e = hipGetDevice(&x->device);
+    if (e == hipSuccess) {
+        if (hip_stream) x->stream = (hipStream_t)hip_stream;
+        else {
+            // a blocking stream: ordered with work on the legacy default stream,
+            // where PyTorch queues by default
+            e = hipStreamCreate(&x->stream);
+            x->own_stream = (e == hipSuccess);
+        }
+    }
+    if (e != hipSuccess) {
+        g_init_error = std::string("HIP: ") + hipGetErrorString(e);
+        release(x);
+        delete x;
+        return HMC_EDEVICE;
+    }
+    st = build(x, net, mask, data, seed);
+    if (st != HMC_OK) {
+        g_init_error = x->err;
+        release(x);
+        delete x;
+        return st;
+    }
+    *out = x;
+    return HMC_OK;
+}
+
+hmc_status hmc_leapfrog(hmc_ctx* x, int32_t n_chains, const int32_t* chain_ids, const double* eps, int32_t L,
+                        hmc_traj_stat* stats) {
+    if (!x) return HMC_EINVAL;
+    if (n_chains < 1 || n_chains > x->C) return x->fail(HMC_EINVAL, "n_chains out of range");
+    HMC_TRY(check_eps(x, eps, n_chains, L));
+    std::vector<double> e(x->C, 0.0);
+    std::vector<int> act(x->C, 0);
+    for (int i = 0; i < n_chains; ++i) {
+        const int c = chain_ids ? chain_ids[i] : i;
+        if (c < 0 || c >= x->C) return x->fail(HMC_EINVAL, "chain id out of range");
+        if (act[c]) return x->fail(HMC_EINVAL, "chain id listed twice");
+        act[c] = 1;
+        e[c] = eps[i];
+    }
+    HMC_TRY(set_eps_active(x, e, act));
+    HMC_TRY(launch_leapfrog(x, x->sa, L, x->stream));
+    HMC_HIP(x, hmc_launch_traj_end(x->prec, x->sa, END_METROPOLIS, x->stream));
+    if (stats) {
+        std::vector<hmc_traj_stat> all(x->C);
+        HMC_HIP(x, hipMemcpyAsync(all.data(), x->sa.stats, sizeof(hmc_traj_stat) * x->C, hipMemcpyDeviceToHost, x->stream));
+        HMC_HIP(x, hipStreamSynchronize(x->stream));
+        for (int i = 0; i < n_chains; ++i) stats[i] = all[chain_ids ? chain_ids[i] : i];
+    }
+    return HMC_OK;
+}
+
+hmc_status hmc_sample(hmc_ctx* x, int64_t n, const double* eps, int32_t L, void* samples, hmc_traj_stat* stats) {
+    if (!x) return HMC_EINVAL;
+    if (n < 0) return x->fail(HMC_EINVAL, "n must be non-negative");
+    HMC_TRY(check_eps(x, eps, x->C, L));
+    if (n == 0) return HMC_OK;
+    HMC_TRY(set_eps_active(x, std::vector<double>(eps, eps + x->C), std::vector<int>(x->C, 1)));
+    HMC_TRY(trajectory_graph(x, L));
+    hmc_traj_stat* pinned = nullptr;
+    if (stats) HMC_HIP(x, hipHostMalloc((void**)&pinned, sizeof(hmc_traj_stat) * x->C * n, hipHostMallocDefault));
+    const size_t sb = (size_t)x->nnz * ssize_of(x->prec);
+    hmc_status st = HMC_OK;
+    for (int64_t i = 0; i < n && st == HMC_OK; ++i) {
+        st = x->hip(hipGraphLaunch(x->gexec, x->stream), "hipGraphLaunch");
+        if (st == HMC_OK && samples)
+            st = x->hip(hipMemcpyAsync((char*)samples + i * sb, x->sa.theta, sb, hipMemcpyDefault, x->stream),
+                        "copy samples");
+        if (st == HMC_OK && pinned)
+            st = x->hip(hipMemcpyAsync(pinned + i * x->C, x->sa.stats, sizeof(hmc_traj_stat) * x->C,
+                                       hipMemcpyDeviceToHost, x->stream), "copy stats");
+    }
+    if (pinned) {
+        const hipError_t e = hipStreamSynchronize(x->stream);
+        if (st == HMC_OK) st = x->hip(e, "hipStreamSynchronize");
+        if (st == HMC_OK) std::memcpy(stats, pinned, sizeof(hmc_traj_stat) * x->C * n);
+        (void)hipHostFree(pinned);
+    }
+    return st;
+}
+
+hmc_status hmc_grad(hmc_ctx* x, double* U, void* g) {
+    if (!x) return HMC_EINVAL;
+    std::vector<int> all(x->C, 1);
+    if (all != x->active_h) HMC_TRY(set_eps_active(x, std::vector<double>(x->C, 0.0), all));
+    HMC_TRY(launch_refresh(x, x->stream));
+    if (g) HMC_HIP(x, hipMemcpyAsync(g, x->sa.grad, (size_t)x->nnz * ssize_of(x->prec), hipMemcpyDefault, x->stream));
+    if (U) HMC_HIP(x, hipMemcpyAsync(U, x->sa.U, sizeof(double) * x->C, hipMemcpyDeviceToHost, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_trajectory(hmc_ctx* x, const void* p0, const double* eps, int32_t L, void* theta_out, void* p_out,
+                          double* H0, double* H1) {
+    if (!x) return HMC_EINVAL;
+    if (!p0) return x->fail(HMC_EINVAL, "p0 is NULL");
+    HMC_TRY(check_eps(x, eps, x->C, L));
+    const size_t sb = (size_t)x->nnz * ssize_of(x->prec);
+    HMC_TRY(set_eps_active(x, std::vector<double>(eps, eps + x->C), std::vector<int>(x->C, 1)));
+    HMC_HIP(x, hipMemcpyAsync(x->pin, p0, sb, hipMemcpyDefault, x->stream));
+    StateArgs s = x->sa;
+    s.p_in = x->pin;
+    HMC_TRY(launch_leapfrog(x, s, L, x->stream));
+    HMC_HIP(x, hmc_launch_traj_end(x->prec, s, END_TRAJ, x->stream));
+    if (theta_out) HMC_HIP(x, hipMemcpyAsync(theta_out, x->sa.theta, sb, hipMemcpyDefault, x->stream));
+    if (p_out) HMC_HIP(x, hipMemcpyAsync(p_out, x->sa.mom, sb, hipMemcpyDefault, x->stream));
+    if (H0) HMC_HIP(x, hipMemcpyAsync(H0, x->sa.H0, sizeof(double) * x->C, hipMemcpyDeviceToHost, x->stream));
+    if (H1) HMC_HIP(x, hipMemcpyAsync(H1, x->sa.H1, sizeof(double) * x->C, hipMemcpyDeviceToHost, x->stream));
+    HMC_HIP(x, hmc_launch_restore(x->prec, x->sa, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_momentum(hmc_ctx* x, uint64_t iteration, void* p_out) {
+    if (!x) return HMC_EINVAL;
+    if (!p_out) return x->fail(HMC_EINVAL, "p_out is NULL");
+    StateArgs s = x->sa;
+    s.iter_override = iteration;
+    s.p_out = x->ptmp;
+    HMC_HIP(x, hmc_launch_momentum(x->prec, s, x->stream));
+    HMC_HIP(x, hipMemcpyAsync(p_out, x->ptmp, (size_t)x->nnz * ssize_of(x->prec), hipMemcpyDefault, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_get_state(hmc_ctx* x, void* theta_s, double* U, uint64_t* iteration) {
+    if (!x) return HMC_EINVAL;
+    if (theta_s)
+        HMC_HIP(x, hipMemcpyAsync(theta_s, x->sa.theta, (size_t)x->nnz * ssize_of(x->prec), hipMemcpyDefault, x->stream));
+    if (U) HMC_HIP(x, hipMemcpyAsync(U, x->sa.U, sizeof(double) * x->C, hipMemcpyDeviceToHost, x->stream));
+    if (iteration)
+        HMC_HIP(x, hipMemcpyAsync(iteration, x->sa.iter, sizeof(uint64_t) * x->C, hipMemcpyDeviceToHost, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_set_state(hmc_ctx* x, const void* theta_s, const uint64_t* iteration) {
+    if (!x) return HMC_EINVAL;
+    if (!theta_s) return x->fail(HMC_EINVAL, "theta_s is NULL");
+    std::vector<int> all(x->C, 1);
+    if (all != x->active_h) HMC_TRY(set_eps_active(x, std::vector<double>(x->C, 0.0), all));
+    HMC_HIP(x, hipMemcpyAsync(x->sa.theta, theta_s, (size_t)x->nnz * ssize_of(x->prec), hipMemcpyDefault, x->stream));
+    if (iteration)
+        HMC_HIP(x, hipMemcpyAsync(x->sa.iter, iteration, sizeof(uint64_t) * x->C, hipMemcpyHostToDevice, x->stream));
+    HMC_HIP(x, hmc_launch_scatter_all(x->prec, x->sa, x->stream));
+    HMC_TRY(launch_refresh(x, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_counters(hmc_ctx* x, int64_t* accepted, int64_t* divergent) {
+    if (!x) return HMC_EINVAL;
+    if (accepted)
+        HMC_HIP(x, hipMemcpyAsync(accepted, x->sa.n_acc, sizeof(int64_t) * x->C, hipMemcpyDeviceToHost, x->stream));
+    if (divergent)
+        HMC_HIP(x, hipMemcpyAsync(divergent, x->sa.n_div, sizeof(int64_t) * x->C, hipMemcpyDeviceToHost, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_get_info(const hmc_ctx* x, hmc_info_t* info) {
+    if (!x || !info) return HMC_EINVAL;
+    info->n_params = x->P;
+    info->nnz = x->nnz;
+    info->n_chains = x->C;
+    info->precision = x->prec;
+    info->kind = x->kind;
+    info->rows_per_tile_a = x->Ra;
+    info->rows_per_tile_b = x->Rb;
+    info->tiles_a = x->tiles_a;
+    info->tiles_b = x->tiles_b;
+    info->device_bytes = x->dev_bytes;
+    return HMC_OK;
+}
+
+hmc_status hmc_time_kernels(hmc_ctx* x, int32_t reps, double* ms) {
+    if (!x) return HMC_EINVAL;
+    if (reps < 1 || !ms) return x->fail(HMC_EINVAL, "reps must be positive and ms non-NULL");
+    std::vector<int> all(x->C, 1);
+    if (all != x->active_h) HMC_TRY(set_eps_active(x, std::vector<double>(x->C, 0.0), all));
+    const int P = x->prec;
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+    auto timed = [&](int slot, auto&& launch) -> hmc_status {
+        HMC_TRY(launch());   // warm
+        HMC_HIP(x, hipEventRecord(x->ev0, x->stream));
+        for (int r = 0; r < reps; ++r) HMC_TRY(launch());
+        HMC_HIP(x, hipEventRecord(x->ev1, x->stream));
+        HMC_HIP(x, hipEventSynchronize(x->ev1));
+        float t = 0;
+        HMC_HIP(x, hipEventElapsedTime(&t, x->ev0, x->ev1));
+        ms[slot] = (double)t / reps;
+        return HMC_OK;
+    };
+    if (x->kind == HMC_MLP) {
+        HMC_TRY(timed(0, [&] { return x->hip(hmc_launch_mlp_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, x->stream), "mlp_grad"); }));
+    } else {
+        HMC_TRY(timed(1, [&] { return x->hip(hmc_launch_trunk_fwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_fwd"); }));
+        HMC_TRY(timed(0, [&] { return x->hip(hmc_launch_branch_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, x->stream), "branch_grad"); }));
+        HMC_TRY(timed(2, [&] { return x->hip(hmc_launch_trunk_bwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_bwd"); }));
+    }
+    HMC_TRY(timed(3, [&] { return x->hip(hmc_launch_update(P, x->sa, UPD_GRAD, update_grid(x), x->stream), "update"); }));
+    // leave U consistent with the gradient just recomputed
+    HMC_HIP(x, hmc_launch_traj_end(P, x->sa, END_ENERGY, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_sync(hmc_ctx* x) {
+    if (!x) return HMC_EINVAL;
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    HMC_HIP(x, hipGetLastError());
+    return HMC_OK;
+}
+
+const char* hmc_last_error(const hmc_ctx* x) { return x ? x->err.c_str() : g_init_error.c_str(); }
+
+void hmc_destroy(hmc_ctx* x) {
+    if (!x) return;
+    release(x);
+    delete x;
+}
+
+}  // extern "C"

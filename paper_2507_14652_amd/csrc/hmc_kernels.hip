@@ -1,0 +1,817 @@
+// gfx950 kernels of the masked full-batch HMC path.
+//
+// One leapfrog step of the sampler (Sec. 2.2, Algorithm 2) needs U and the
+// gradient of U with respect to the selected entries Theta_s.  The tile
+// kernels below compute them for one (chain, row tile) per workgroup:
+//   forward pass of every layer (MFMA products with the bias and tanh fused
+//   into the epilogue), the squared-error head in FP64, the adjoint pass with
+//   the tanh derivative fused into its epilogue, and the per-tile partial
+//   sums of only those weight-gradient entries that the mask selects.
+// Activations never leave LDS.  Per-tile partials are then summed in a fixed
+// order by the update kernel, which also applies the prior term, the kick,
+// the drift and the scatter of the new positions into the dense weights.
+//
+// Product tiles use the 16x16 MFMA shapes of CDNA4: f64 16x16x4, f32 16x16x4
+// and bf16 16x16x32 (f32 accumulation).  Each lane supplies row (lane % 16)
+// of the A operand and column (lane % 16) of the B operand with K-slots
+// picked by lane / 16; it receives four accumulator rows of column lane % 16:
+// rows 4 * (lane / 16) + v for f32 and bf16, rows lane / 16 + 4 v for f64
+// (measured on gfx950; the f64 A rows are permuted to match the f32 layout).
+// Any K permutation that both
+// operands share leaves the product unchanged, so a lane loads VEC
+// consecutive K values per 16-byte (or 32-byte) access and feeds them to
+// successive K-slots.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "hmc_launch.hpp"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int NWAVE = HMC_NT / 64;
+
+template <int P> struct PT;
+template <> struct PT<0> {
+    typedef double T;  typedef double A;  typedef double S;
+    typedef d4v Acc;   typedef d4v Frag;  typedef d4v O4;
+    static constexpr int KCH = 16, VEC = 4;
+};
+template <> struct PT<1> {
+    typedef float T;   typedef float A;   typedef float S;
+    typedef f4v Acc;   typedef f4v Frag;  typedef f4v O4;
+    static constexpr int KCH = 16, VEC = 4;
+};
+template <> struct PT<2> {
+    typedef __bf16 T;  typedef float A;   typedef float S;
+    typedef f4v Acc;   typedef b8v Frag;  typedef b4v O4;
+    static constexpr int KCH = 32, VEC = 8;
+};
+
+__device__ __forceinline__ void mma(d4v& c, const d4v& a, const d4v& b) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f4v& c, const f4v& a, const f4v& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f4v& c, const b8v& a, const b8v& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double act_tanh(double x) { return tanh(x); }
+__device__ __forceinline__ float act_tanh(float x) { return tanhf(x); }
+
+// ---------------------------------------------------------------------------
+// Workgroup -> (chain, tile).  Consecutive workgroup ids are dealt round-robin
+// to the 8 XCDs, each with its own L2; the remap gives every XCD a contiguous
+// range of logical tiles so that the tiles of one chain share the L2 that
+// holds that chain's weights.  The grid is padded to a multiple of 8.
+__device__ __forceinline__ bool tile_of(int total, int per_chain, int& c, int& t) {
+    const int w = blockIdx.x;
+    const int per_xcd = gridDim.x >> 3;
+    const int logical = (w & 7) * per_xcd + (w >> 3);
+    if (logical >= total) return false;
+    c = logical / per_chain;
+    t = logical - c * per_chain;
+    return true;
+}
+
+// Deterministic workgroup sum: fixed butterfly within each wave, then the four
+// wave sums in wave order.  Every thread returns the same value.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = scratch[0];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w) s += scratch[w];
+    __syncthreads();
+    return s;
+}
+
+// Copies R rows of a dense [rows][w] global block into an LDS slab of row
+// stride ld, 16 bytes per access.
+template <class T, int R>
+__device__ __forceinline__ void load_rows(T* dst, int ld, const T* src, int w) {
+    constexpr int E = 16 / sizeof(T);
+    const int cpr = w / E;
+    for (int i = threadIdx.x; i < R * cpr; i += HMC_NT) {
+        const int r = i / cpr, q = i - r * cpr;
+        *reinterpret_cast<uint4*>(dst + r * ld + q * E) =
+            *reinterpret_cast<const uint4*>(src + (size_t)r * w + q * E);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile product: for n in [0, Np) and r in [0, R)
+//     out^T[n][r] = sum_{k < K} Wm[n][k] * X[r][k]
+// Wm row stride ldw, X row stride ldx (LDS or global).  Work units are
+// (16-column block of n, NRB 16-row blocks of r); the A fragment (weights)
+// is loaded once per K chunk and reused over the NRB row blocks.
+template <int P, int R, int NRB, class Epi>
+__device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__ Wm, int ldw, int K, int Np,
+                                           const typename PT<P>::T* X, int ldx, Epi& epi) {
+    typedef typename PT<P>::T T;
+    typedef typename PT<P>::Acc Acc;
+    typedef typename PT<P>::Frag Frag;
+    constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
+    constexpr int RG = (R / 16) / NRB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    // f64 16x16x4 returns accumulator rows g + 4v (f32 and bf16: 4g + v);
+    // feeding A row 4 * (li % 4) + li / 4 from lane li makes the f64 outputs
+    // land on rows 4g + v as well, so every epilogue sees the same layout.
+    const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
+    const int units = (Np >> 4) * RG;
+    for (int u = wave; u < units; u += NWAVE) {
+        const int nb = u / RG, rg = u - nb * RG;
+        Acc acc[NRB];
+#pragma unroll
+        for (int i = 0; i < NRB; ++i) acc[i] = Acc{};
+        const T* wr = Wm + (size_t)(nb * 16 + arow) * ldw + g * VEC;
+        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
+        for (int k0 = 0; k0 < K; k0 += KCH) {
+            const Frag a = *reinterpret_cast<const Frag*>(wr + k0);
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) {
+                const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + k0);
+                mma(acc[i], a, b);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NRB; ++i) epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, acc[i]);
+    }
+}
+
+template <int P, int R, class Epi>
+__device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K, int Np,
+                                     const typename PT<P>::T* X, int ldx, Epi& epi) {
+    if ((Np >> 4) >= NWAVE) gemm_units<P, R, R / 16>(Wm, ldw, K, Np, X, ldx, epi);
+    else gemm_units<P, R, 1>(Wm, ldw, K, Np, X, ldx, epi);
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues.  Each receives the output row r of the tile, the first of four
+// consecutive output columns n0 and the four accumulators.
+
+// Hidden layer: a = tanh(z + b), stored in the product precision.
+template <int P> struct EpiTanh {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const A* bias; T* out; int ld;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = (T)act_tanh((A)acc[v] + bias[n0 + v]);
+        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+    }
+};
+
+// Plain store (adjoints of linear outputs).
+template <int P> struct EpiStore {
+    typedef typename PT<P>::T T;
+    T* out; int ld;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = (T)acc[v];
+        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+    }
+};
+
+// Adjoint through tanh: delta_in = (delta_out W) * (1 - a^2), in place over a.
+template <int P> struct EpiBack {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    T* io; int ld;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        typename PT<P>::O4* p = reinterpret_cast<typename PT<P>::O4*>(io + r * ld + n0);
+        const typename PT<P>::O4 a = *p;
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const A av = (A)a[v];
+            o[v] = (T)((A)acc[v] * ((A)1 - av * av));
+        }
+        *p = o;
+    }
+};
+
+// MLP output layer and squared-error head: F = z + b; residual in FP64;
+// delta = (F - y) / lik_sd^2 replaces the output; the squared residuals of
+// the valid rows accumulate per thread.
+template <int P> struct EpiMlpHead {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const A* bias; T* out; int ld;
+    const double* y; int d_out; int row0; int nrows; double iv;
+    double sq;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) {
+        typename PT<P>::O4 o;
+        const int row = row0 + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + v;
+            T d = (T)0;
+            if (n < d_out && row < nrows) {
+                const double res = ((double)acc[v] + (double)bias[n]) - y[(size_t)row * d_out + n];
+                sq += res * res;
+                d = (T)(A)(res * iv);
+            }
+            o[v] = d;
+        }
+        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+    }
+};
+
+// Branch output layer: B = z + b kept in LDS for the combination, and B^T
+// written to global memory for the trunk adjoint (zero for padded rows).
+template <int P> struct EpiBranchOut {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const A* bias; T* out; int ld; T* bt; int bt_ld; int col0; int nvalid;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T tv = (T)((A)acc[v] + bias[n0 + v]);
+            o[v] = tv;
+            bt[(size_t)(n0 + v) * bt_ld + col0 + r] = (r < nvalid) ? tv : (T)0;
+        }
+        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+    }
+};
+
+// Trunk output layer: T = z + b, written to global memory both as [q][k] and
+// as [k][q] (zero for padded query rows).
+template <int P> struct EpiTrunkOut {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const A* bias; T* tm; int tm_ld; T* tt; int tt_ld; int row0; int nvalid;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        typename PT<P>::O4 o;
+        const bool ok = r < nvalid;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T tv = ok ? (T)((A)acc[v] + bias[n0 + v]) : (T)0;
+            o[v] = tv;
+            tt[(size_t)(n0 + v) * tt_ld + row0 + r] = tv;
+        }
+        *reinterpret_cast<typename PT<P>::O4*>(tm + (size_t)(row0 + r) * tm_ld + n0) = o;
+    }
+};
+
+// DeepONet combination and head: G[a][q] = <B_a, T_q> + b0 arrives as the
+// transposed tile (rows q, columns a); residual in FP64; the output adjoint
+// dG = (G - v) / lik_sd^2 goes to an LDS slab [a][q] and to global [q][a];
+// squared residuals and the b0 gradient accumulate per thread.
+template <int P> struct EpiCombine {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    T* dg; int dg_ld; T* dgt; int dgt_ld; int col0;
+    const double* v; int nq; int nvalid; int row0; double b0; double iv;
+    double sq; double sdg;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) {
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int q = n0 + w;
+            T d = (T)0;
+            if (q < nq && r < nvalid) {
+                const double res = ((double)acc[w] + b0) - v[(size_t)(row0 + r) * nq + q];
+                sq += res * res;
+                const double dd = res * iv;
+                sdg += dd;
+                d = (T)(A)dd;
+            }
+            o[w] = d;
+            dgt[(size_t)q * dgt_ld + col0 + r] = d;
+        }
+        *reinterpret_cast<typename PT<P>::O4*>(dg + r * dg_ld + n0) = o;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Masked weight gradient, one tile: for each selected entry k of the layer,
+//   part[k] = sum_r delta[r][i_k] * a[r][j_k]     (weights)
+//   part[k] = sum_r delta[r][i_k]                  (biases)
+// Rows past the data hold delta = 0 and contribute nothing.
+template <int P, int R>
+__device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0, int k1,
+                                            const typename PT<P>::T* D, int ld,
+                                            const typename PT<P>::T* X, int lx,
+                                            typename PT<P>::A* __restrict__ part) {
+    typedef typename PT<P>::A A;
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += HMC_NT) {
+        const int cd = code[k];
+        const int i = cd >> 16, j = cd & 0xFFFF;
+        A s = (A)0;
+        if (j == 0xFFFF) {
+#pragma unroll 8
+            for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
+        } else {
+#pragma unroll 8
+            for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+        }
+        part[k] = s;
+    }
+}
+
+template <int P, int R>
+__device__ __forceinline__ void tower_hidden_forward(const TowerPlan& tp, const typename PT<P>::T* W,
+                                                     const typename PT<P>::A* B, typename PT<P>::T* sm) {
+    for (int l = 0; l < tp.nl - 1; ++l) {
+        EpiTanh<P> e{B + tp.bo[l], sm + tp.lo[l + 1], tp.ls[l + 1]};
+        gemm<P, R>(W + tp.wo[l], tp.wp[l], tp.wp[l], tp.wp[l + 1], sm + tp.lo[l], tp.ls[l], e);
+        __syncthreads();
+    }
+}
+
+// Adjoint pass of one tower from the output adjoint held in slab nl: for each
+// layer from the top, the selected weight-gradient partials, then (while a
+// lower layer still has selected entries) the adjoint of the layer input.
+template <int P, int R>
+__device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, int c, int t,
+                                               const typename PT<P>::T* W, typename PT<P>::T* sm) {
+    typedef typename PT<P>::A A;
+    const long long o = a.offs[c];
+    const int n = (int)(a.offs[c + 1] - o);
+    const int* code = a.ecode + o;
+    const int* seg = a.seg + (size_t)c * a.nseg + tp.seg0;
+    A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)t * n;
+    int lowest = tp.nl;
+    for (int l = 0; l < tp.nl; ++l)
+        if (seg[l + 1] > seg[l]) { lowest = l; break; }
+    for (int l = tp.nl - 1; l >= lowest; --l) {
+        dw_partials<P, R>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+        if (l > lowest) {
+            __syncthreads();
+            EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};
+            gemm<P, R>(W + tp.wto[l], tp.wp[l + 1], tp.wp[l + 1], tp.wp[l], sm + tp.lo[l + 1], tp.ls[l + 1], e);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MLP: forward, head and adjoint of one (chain, row tile).
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    double* red = reinterpret_cast<double*>(smem + a.red_off);
+    int c, t;
+    if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    const int L = tp.nl - 1;
+    EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target, a.d_out, t * R, a.n_rows_a,
+                    a.inv_lik_var, 0.0};
+    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
+    const double sq = block_sum(h.sq, red);
+    if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
+    tower_backward<P, R>(a, tp, c, t, W, sm);
+}
+
+// DeepONet trunk forward: T = trunk(y_q) for one (chain, query tile).
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_trunk_fwd(const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    int c, t;
+    if (!tile_of(a.n_chains * a.tiles_b, a.tiles_b, c, t)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.tb;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xb) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    const int L = tp.nl - 1;
+    const int nvalid = a.n_rows_b - t * R;
+    EpiTrunkOut<P> e{B + tp.bo[L], reinterpret_cast<T*>(a.tm) + c * a.tm_stride, tp.wp[L + 1],
+                     reinterpret_cast<T*>(a.tt) + c * a.tm_stride, a.nq_rows, t * R, nvalid};
+    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], e);
+}
+
+// DeepONet branch tile: branch forward, combination with the trunk features,
+// FP64 head, adjoint of the branch output, branch adjoint pass.
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    double* red = reinterpret_cast<double*>(smem + a.red_off);
+    int c, t;
+    if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    const int L = tp.nl - 1;
+    const int pp = tp.wp[L + 1];
+    const int nvalid = a.n_rows_a - t * R;
+    EpiBranchOut<P> eo{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1],
+                       reinterpret_cast<T*>(a.btr) + c * a.bt_stride, a.nu_cols, t * R, nvalid};
+    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], pp, sm + tp.lo[L], tp.ls[L], eo);
+    __syncthreads();
+    EpiCombine<P> ec{sm + a.dg_off, a.dg_ld, reinterpret_cast<T*>(a.dgt) + c * a.dgt_stride, a.nu_cols, t * R,
+                     a.target, a.nq, nvalid, t * R, (double)B[a.b0_off], a.inv_lik_var, 0.0, 0.0};
+    gemm<P, R>(reinterpret_cast<const T*>(a.tm) + c * a.tm_stride, pp, pp, a.nq_pad, sm + tp.lo[L + 1],
+               tp.ls[L + 1], ec);
+    const double sq = block_sum(ec.sq, red);
+    const double sdg = block_sum(ec.sdg, red);
+    if (threadIdx.x == 0) {
+        a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
+        const long long o = a.offs[c];
+        const int n = (int)(a.offs[c + 1] - o);
+        const int* seg = a.seg + (size_t)c * a.nseg;
+        const int kb0 = seg[a.nseg - 2];
+        if (seg[a.nseg - 1] > kb0)
+            reinterpret_cast<A*>(a.part)[a.tmax * o + (long long)t * n + kb0] = (A)sdg;
+    }
+    // adjoint of the branch output: dB = dG T, into the slab that held B
+    EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
+    gemm<P, R>(reinterpret_cast<const T*>(a.tt) + c * a.tm_stride, a.nq_rows, a.nq_pad, pp, sm + a.dg_off,
+               a.dg_ld, es);
+    __syncthreads();
+    tower_backward<P, R>(a, tp, c, t, W, sm);
+}
+
+// DeepONet trunk adjoint tile: recompute the trunk forward for the tile's
+// query rows, form dT = dG^T B for those rows (reduction over all
+// functions), then the trunk adjoint pass.
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    int c, t;
+    if (!tile_of(a.n_chains * a.tiles_b, a.tiles_b, c, t)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.tb;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xb) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    const int L = tp.nl - 1;
+    EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
+    gemm<P, R>(reinterpret_cast<const T*>(a.btr) + c * a.bt_stride, a.nu_cols, a.nu_cols, tp.wp[L + 1],
+               reinterpret_cast<const T*>(a.dgt) + c * a.dgt_stride + (size_t)t * R * a.nu_cols, a.nu_cols, es);
+    __syncthreads();
+    tower_backward<P, R>(a, tp, c, t, W, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Per-entry state kernels.
+
+template <int P>
+__device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, typename PT<P>::S x) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const int d0 = s.dst[2 * e], d1 = s.dst[2 * e + 1];
+    if (d0 >= 0) {
+        T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;
+        W[d0] = (T)x;
+        W[d1] = (T)x;
+    } else {
+        reinterpret_cast<A*>(s.bbuf)[c * s.bstride + (-d0 - 1)] = (A)x;
+    }
+}
+
+// Sum of the per-tile partials in tile order, plus the prior term, then the
+// kick (and drift + scatter) of the leapfrog step.
+template <int P>
+__global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode) {
+    typedef typename PT<P>::A A; typedef typename PT<P>::S S;
+    const int c = blockIdx.y;
+    if (!s.active[c]) return;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int* seg = s.seg + (size_t)c * s.nseg;
+    const int nt = (k >= seg[s.seg_trunk_lo] && k < seg[s.seg_trunk_hi]) ? s.tiles_b : s.tiles_a;
+    const A* pp = reinterpret_cast<const A*>(s.part) + s.tmax * o + k;
+    A acc = (A)0;
+    for (int t = 0; t < nt; ++t) acc += pp[(size_t)t * n];
+    S* th = reinterpret_cast<S*>(s.theta) + o;
+    S x = th[k];
+    const S g = (S)acc + x * (S)s.inv_prior_var;
+    reinterpret_cast<S*>(s.grad)[o + k] = g;
+    if (mode == UPD_GRAD) return;
+    const S e = (S)s.eps[c];
+    S* mo = reinterpret_cast<S*>(s.mom) + o;
+    S p = mo[k];
+    if (mode == UPD_HALF_KICK) {
+        mo[k] = p - (S)0.5 * e * g;
+        return;
+    }
+    p = p - e * g;
+    mo[k] = p;
+    const S m = s.minv ? reinterpret_cast<const S*>(s.minv)[o + k] : (S)1;
+    x = x + e * m * p;
+    th[k] = x;
+    scatter<P>(s, c, o + k, x);
+}
+
+__device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0, unsigned long long k1) {
+    const unsigned long long M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const unsigned long long W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        const unsigned long long hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const unsigned long long hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u01(unsigned long long w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+// Four standard normals of Philox block `blk` of the momentum stream.
+__device__ __forceinline__ void normals4(unsigned long long seed, int chain, unsigned long long it,
+                                         unsigned long long blk, double z[4]) {
+    unsigned long long c[4] = {it, 0ull, blk, 0ull};
+    philox4x64_10(c, seed, (unsigned long long)chain);
+    const double two_pi = 6.283185307179586;
+    const double r0 = sqrt(-2.0 * log(u01(c[0]))), r1 = sqrt(-2.0 * log(u01(c[2])));
+    const double t0 = two_pi * u01(c[1]), t1 = two_pi * u01(c[3]);
+    z[0] = r0 * cos(t0); z[1] = r0 * sin(t0);
+    z[2] = r1 * cos(t1); z[3] = r1 * sin(t1);
+}
+
+__device__ __forceinline__ double metropolis_u(unsigned long long seed, int chain, unsigned long long it) {
+    unsigned long long c[4] = {it, 1ull, 0ull, 0ull};
+    philox4x64_10(c, seed, (unsigned long long)chain);
+    return u01(c[0]);
+}
+
+// Start of a trajectory (one workgroup per chain): momentum refresh (or the
+// injected momentum), save of the current state, kinetic energy and H0 in
+// FP64, first half kick with the cached gradient, first drift and scatter.
+template <int P>
+__global__ __launch_bounds__(256) void k_traj_begin(const StateArgs s) {
+    typedef typename PT<P>::S S;
+    __shared__ double red[NWAVE];
+    const int c = blockIdx.x;
+    if (!s.active[c]) return;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    const S e = (S)s.eps[c];
+    const unsigned long long it = s.iter[c];
+    S* th = reinterpret_cast<S*>(s.theta) + o;
+    S* gr = reinterpret_cast<S*>(s.grad) + o;
+    S* mo = reinterpret_cast<S*>(s.mom) + o;
+    S* ths = reinterpret_cast<S*>(s.theta_save) + o;
+    S* grs = reinterpret_cast<S*>(s.grad_save) + o;
+    const S* minv = s.minv ? reinterpret_cast<const S*>(s.minv) + o : nullptr;
+    const S* pin = s.p_in ? reinterpret_cast<const S*>(s.p_in) + o : nullptr;
+    double kin = 0.0;
+    for (int b = threadIdx.x; 4 * b < n; b += 256) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!pin) normals4(s.seed, c, it, (unsigned long long)b, z);
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * b + j;
+            if (k >= n) break;
+            const S m = minv ? minv[k] : (S)1;
+            S p = pin ? pin[k] : (S)(z[j] / sqrt((double)m));
+            S x = th[k];
+            const S g = gr[k];
+            ths[k] = x;
+            grs[k] = g;
+            kin += 0.5 * (double)m * (double)p * (double)p;
+            p = p - (S)0.5 * e * g;
+            x = x + e * m * p;
+            mo[k] = p;
+            th[k] = x;
+            scatter<P>(s, c, o + k, x);
+        }
+    }
+    kin = block_sum(kin, red);
+    if (threadIdx.x == 0) {
+        s.H0[c] = s.U[c] + kin;
+        s.U_save[c] = s.U[c];
+    }
+}
+
+struct DevStat { double H0, H1, log_u; int accepted, divergent; };
+
+// End of a trajectory (one workgroup per chain).  END_ENERGY: U = likelihood
+// partials + prior, stored as the current U.  END_TRAJ: also the kinetic
+// energy and H1, state untouched.  END_METROPOLIS: accept iff
+// log u < H0 - H1 with H1 finite; on rejection restore position, gradient
+// and U; record the outcome and advance the iteration counter.
+template <int P>
+__global__ __launch_bounds__(256) void k_traj_end(const StateArgs s, int mode) {
+    typedef typename PT<P>::S S;
+    __shared__ double red[NWAVE];
+    const int c = blockIdx.x;
+    if (!s.active[c]) return;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    S* th = reinterpret_cast<S*>(s.theta) + o;
+    const S* mo = reinterpret_cast<const S*>(s.mom) + o;
+    const S* minv = s.minv ? reinterpret_cast<const S*>(s.minv) + o : nullptr;
+    double pri = 0.0, kin = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const double x = (double)th[k];
+        pri += x * x;
+        if (mode != END_ENERGY) {
+            const double p = (double)mo[k];
+            kin += (minv ? (double)minv[k] : 1.0) * p * p;
+        }
+    }
+    pri = 0.5 * s.inv_prior_var * block_sum(pri, red);
+    kin = 0.5 * block_sum(kin, red);
+    double ul = 0.0;
+    for (int t = 0; t < s.tiles_a; ++t) ul += s.ulik[(size_t)c * s.tiles_a + t];
+    const double U1 = ul + pri;
+    if (mode == END_ENERGY) {
+        if (threadIdx.x == 0) s.U[c] = U1;
+        return;
+    }
+    const double H1 = U1 + kin;
+    if (mode == END_TRAJ) {
+        if (threadIdx.x == 0) s.H1[c] = H1;
+        return;
+    }
+    const double H0 = s.H0[c];
+    const unsigned long long it = s.iter[c];
+    const double lu = log(metropolis_u(s.seed, c, it));
+    const bool fin = isfinite(H1);
+    const bool acc = fin && (lu < H0 - H1);
+    if (!acc) {
+        S* gr = reinterpret_cast<S*>(s.grad) + o;
+        const S* ths = reinterpret_cast<const S*>(s.theta_save) + o;
+        const S* grs = reinterpret_cast<const S*>(s.grad_save) + o;
+        for (int k = threadIdx.x; k < n; k += 256) {
+            const S x = ths[k];
+            th[k] = x;
+            gr[k] = grs[k];
+            scatter<P>(s, c, o + k, x);
+        }
+    }
+    if (threadIdx.x == 0) {
+        s.U[c] = acc ? U1 : s.U_save[c];
+        s.H1[c] = H1;
+        DevStat st{H0, H1, lu, acc ? 1 : 0, fin ? 0 : 1};
+        reinterpret_cast<DevStat*>(s.stats)[c] = st;
+        s.n_acc[c] += acc ? 1 : 0;
+        s.n_div[c] += fin ? 0 : 1;
+        s.iter[c] = it + 1;
+    }
+}
+
+// The momentum that iteration `iter_override` would draw (no state change).
+template <int P>
+__global__ __launch_bounds__(256) void k_momentum(const StateArgs s) {
+    typedef typename PT<P>::S S;
+    const int c = blockIdx.x;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    S* out = reinterpret_cast<S*>(s.p_out) + o;
+    const S* minv = s.minv ? reinterpret_cast<const S*>(s.minv) + o : nullptr;
+    for (int b = threadIdx.x; 4 * b < n; b += 256) {
+        double z[4];
+        normals4(s.seed, c, s.iter_override, (unsigned long long)b, z);
+        for (int j = 0; j < 4 && 4 * b + j < n; ++j) {
+            const int k = 4 * b + j;
+            const double m = minv ? (double)minv[k] : 1.0;
+            out[k] = (S)(z[j] / sqrt(m));
+        }
+    }
+}
+
+// Puts back the state saved at the start of a trajectory.
+template <int P>
+__global__ __launch_bounds__(256) void k_restore(const StateArgs s) {
+    typedef typename PT<P>::S S;
+    const int c = blockIdx.x;
+    if (!s.active[c]) return;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const S x = reinterpret_cast<const S*>(s.theta_save)[o + k];
+        reinterpret_cast<S*>(s.theta)[o + k] = x;
+        reinterpret_cast<S*>(s.grad)[o + k] = reinterpret_cast<const S*>(s.grad_save)[o + k];
+        scatter<P>(s, c, o + k, x);
+    }
+    if (threadIdx.x == 0) s.U[c] = s.U_save[c];
+}
+
+// Writes every chain's current positions into its dense weights.
+template <int P>
+__global__ __launch_bounds__(256) void k_scatter_all(const StateArgs s) {
+    typedef typename PT<P>::S S;
+    const int c = blockIdx.x;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    for (int k = threadIdx.x; k < n; k += 256)
+        scatter<P>(s, c, o + k, reinterpret_cast<const S*>(s.theta)[o + k]);
+}
+
+template <int P, int R>
+hipError_t set_lds(size_t lds) {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    return hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+#define HMC_DISPATCH_PR(P, R, CALL)                                            \
+    switch ((P) * 100 + (R)) {                                                 \
+        case 16: CALL(0, 16); case 32: CALL(0, 32); case 64: CALL(0, 64);     \
+        case 116: CALL(1, 16); case 132: CALL(1, 32); case 164: CALL(1, 64);  \
+        case 216: CALL(2, 16); case 232: CALL(2, 32); case 264: CALL(2, 64);  \
+        default: return hipErrorInvalidValue;                                  \
+    }
+
+#define HMC_DISPATCH_P(P, CALL)                                                \
+    switch (P) {                                                               \
+        case 0: CALL(0); case 1: CALL(1); case 2: CALL(2);                     \
+        default: return hipErrorInvalidValue;                                  \
+    }
+
+hipError_t hmc_set_lds_limit(int P, int R, size_t lds) {
+#define C_(p, r) return set_lds<p, r>(lds)
+    HMC_DISPATCH_PR(P, R, C_)
+#undef C_
+}
+
+#define HMC_TILE_CALL_k_mlp_grad(p, r) \
+    hipLaunchKernelGGL((k_mlp_grad<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+#define HMC_TILE_CALL_k_trunk_fwd(p, r) \
+    hipLaunchKernelGGL((k_trunk_fwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+#define HMC_TILE_CALL_k_branch_grad(p, r) \
+    hipLaunchKernelGGL((k_branch_grad<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+#define HMC_TILE_CALL_k_trunk_bwd(p, r) \
+    hipLaunchKernelGGL((k_trunk_bwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+
+hipError_t hmc_launch_mlp_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_mlp_grad)
+}
+hipError_t hmc_launch_trunk_fwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_trunk_fwd)
+}
+hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_branch_grad)
+}
+hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_trunk_bwd)
+}
+
+hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_update<p>), dim3(gx, s.n_chains), dim3(256), 0, st, s, mode); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_traj_begin<p>), dim3(s.n_chains), dim3(256), 0, st, s); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_traj_end<p>), dim3(s.n_chains), dim3(256), 0, st, s, mode); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+hipError_t hmc_launch_momentum(int P, const StateArgs& s, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_momentum<p>), dim3(s.n_chains), dim3(256), 0, st, s); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+hipError_t hmc_launch_restore(int P, const StateArgs& s, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_restore<p>), dim3(s.n_chains), dim3(256), 0, st, s); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+hipError_t hmc_launch_scatter_all(int P, const StateArgs& s, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_scatter_all<p>), dim3(s.n_chains), dim3(256), 0, st, s); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}

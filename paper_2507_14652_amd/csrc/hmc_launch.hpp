@@ -1,0 +1,18 @@
+// Host-callable launchers of the gfx950 kernels (defined in hmc_kernels.hip).
+// P selects the number format (0 FP64, 1 FP32, 2 BF16); R is the row-tile
+// height (16, 32 or 64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "hmc_plan.hpp"
+
+hipError_t hmc_set_lds_limit(int P, int R, size_t lds_bytes);
+hipError_t hmc_launch_mlp_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_trunk_fwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
+hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
+hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);
+hipError_t hmc_launch_momentum(int P, const StateArgs& s, hipStream_t st);
+hipError_t hmc_launch_restore(int P, const StateArgs& s, hipStream_t st);
+hipError_t hmc_launch_scatter_all(int P, const StateArgs& s, hipStream_t st);

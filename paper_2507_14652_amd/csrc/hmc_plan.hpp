@@ -1,0 +1,109 @@
+// Plan structures shared by the host engine and the gfx950 kernels.
+//
+// Layout decisions (per chain, in device memory):
+//  * weights in the product precision T, each layer twice: W_l [out_p][in_p]
+//    for the forward product and W_l^T [in_p][out_p] for the adjoint product,
+//    both row-major and zero-padded to the width padding of the precision;
+//  * biases (and the DeepONet b0) in the accumulator precision A;
+//  * activations of one row tile live in LDS, one [R][width_p + pad] slab per
+//    layer; the adjoint of a layer overwrites the activation slab it no
+//    longer needs.
+#pragma once
+#include <stdint.h>
+
+#define HMC_MAXL 8    // linear layers per tower
+#define HMC_NT 256    // threads per workgroup of the tile kernels (4 waves)
+
+struct TowerPlan {
+    int nl;                     // linear layers
+    int w[HMC_MAXL + 1];        // true widths
+    int wp[HMC_MAXL + 1];       // padded widths
+    int ls[HMC_MAXL + 1];       // LDS row stride (elements) of activation slab l
+    int lo[HMC_MAXL + 1];       // LDS offset (elements) of activation slab l
+    long long wo[HMC_MAXL];     // offset of W_l in the per-chain weight buffer
+    long long wto[HMC_MAXL];    // offset of W_l^T
+    long long bo[HMC_MAXL];     // offset of b_l in the per-chain bias buffer
+    int seg0;                   // first layer of this tower in the segment table
+};
+
+// Arguments of the tile kernels (forward, loss head, adjoint, masked
+// weight-gradient partials).
+struct GradArgs {
+    TowerPlan ta;               // MLP or branch tower
+    TowerPlan tb;               // trunk tower (DeepONet)
+    const void* wbuf;           // [C][wstride] T
+    long long wstride;
+    const void* bbuf;           // [C][bstride] A
+    long long bstride;
+    const void* xa;             // tower-A input rows [tiles_a * R_a][wp_a0] T
+    const void* xb;             // trunk input rows [tiles_b * R_b][wp_b0] T
+    const double* target;       // MLP y [N][d_out]; DeepONet v [n_u][n_q]
+    int n_rows_a;               // valid rows of tower A (N or n_u)
+    int n_rows_b;               // valid rows of the trunk (n_q)
+    int d_out;                  // MLP output width
+    int tiles_a, tiles_b;
+    int n_chains;
+    const int* active;          // [C]
+    const long long* offs;      // [C+1]
+    const int* ecode;           // [nnz] (i << 16) | j, j = 0xFFFF for a bias
+    const int* seg;             // [C][nseg] chain-local start of each layer's entries
+    int nseg;
+    void* part;                 // per-tile gradient partials, A
+    long long tmax;             // tiles per chain in the partial layout
+    double* ulik;               // [C][tiles_a] likelihood partials
+    double inv_lik_var;
+    // DeepONet exchange buffers, T
+    void* tm;                   // [C][nq_rows][p_p]   trunk features
+    void* tt;                   // [C][p_p][nq_rows]   trunk features, transposed
+    void* btr;                  // [C][p_p][nu_cols]   branch features, transposed
+    void* dgt;                  // [C][nq_rows][nu_cols] output adjoint, transposed
+    long long tm_stride, bt_stride, dgt_stride;
+    int nq, nq_pad, nq_rows, nu_cols;
+    long long b0_off;           // b0 position in the bias buffer
+    int dg_off;                 // LDS offset (elements) of the [R][nq_pad + pad] output-adjoint slab
+    int dg_ld;
+    int red_off;                // LDS byte offset of the reduction scratch
+};
+
+// Arguments of the per-entry kernels (reduction of partials, kicks, drifts,
+// scatter into the dense weights, momentum refresh, Metropolis step).
+struct StateArgs {
+    int n_chains;
+    const int* active;
+    const long long* offs;
+    const int* seg;
+    int nseg;
+    int seg_trunk_lo, seg_trunk_hi;   // segment indices bounding the trunk entries
+    int tiles_a, tiles_b;
+    long long tmax;
+    const void* part;
+    const double* ulik;
+    void* theta;                // S [nnz]
+    void* mom;                  // S [nnz]
+    void* grad;                 // S [nnz]
+    void* theta_save;           // S [nnz]
+    void* grad_save;            // S [nnz]
+    const void* minv;           // S [nnz] or null (identity)
+    const void* p_in;           // S [nnz] injected momentum or null
+    void* p_out;                // S [nnz] momentum output (refresh preview)
+    const int* dst;             // [2 * nnz] scatter destinations
+    void* wbuf;
+    long long wstride;
+    void* bbuf;
+    long long bstride;
+    const double* eps;          // [C]
+    double inv_prior_var;
+    double* U;                  // [C]
+    double* U_save;             // [C]
+    double* H0;                 // [C]
+    double* H1;                 // [C]
+    unsigned long long* iter;   // [C]
+    unsigned long long seed;
+    unsigned long long iter_override;   // used by the momentum preview
+    void* stats;                // hmc_traj_stat [C]
+    long long* n_acc;           // [C]
+    long long* n_div;           // [C]
+};
+
+enum { UPD_GRAD = 0, UPD_KICK_DRIFT = 1, UPD_HALF_KICK = 2 };
+enum { END_ENERGY = 0, END_TRAJ = 1, END_METROPOLIS = 2 };

@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every function that include/hmc.h
+declares, and rejects invalid arguments on the host before any device work
+(these calls never reach the GPU)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmc.h")
+
+binding = pytest.importorskip("paper_2507_14652_amd.binding")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(binding.LIB_PATH), reason="libhmc.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:hmc_status|const char\*|void)\s+(hmc_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_binding_functions():
+    assert declared_functions() == sorted(binding.ABI_FUNCTIONS)
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _init(**over):
+    """Calls hmc_init with a valid small MLP description, with overrides."""
+    lib = binding.load()
+    B = binding
+    wa = np.array(over.pop("widths_a", [2, 3, 1]), dtype=np.int32)
+    P = int(sum(wa[i] * wa[i + 1] + wa[i + 1] for i in range(len(wa) - 1)))
+    n_params = over.pop("n_params", P)
+    theta0 = np.zeros(max(P, 1))
+    offs = np.array(over.pop("offs", [0, 3]), dtype=np.int64)
+    idx = np.array(over.pop("idx", [0, 4, 7]), dtype=np.int64)
+    x = np.zeros((5, int(wa[0])))
+    y = np.zeros((5, int(wa[-1])))
+    net = B.NetDesc(over.pop("kind", 0), len(wa), wa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0, None,
+                    theta0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_params,
+                    over.pop("prior_sd", 1.0), over.pop("lik_sd", 1.0), over.pop("precision", 1), None)
+    mask = B.MaskDesc(len(offs) - 1, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None)
+    n_rows = over.pop("n_rows", 5)
+    data = B.DataDesc(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if not over.pop("no_y", False) else None,
+                      n_rows, None, None, None, 0, 0)
+    assert not over
+    ctx = ctypes.c_void_p()
+    st = lib.hmc_init(ctypes.byref(ctx), ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), 0, None)
+    return st, ctx, lib.hmc_last_error(None).decode()
+
+
+@needs_lib
+@pytest.mark.parametrize("over,needle", [
+    (dict(n_params=12), "n_params"),
+    (dict(idx=[0, 7, 4]), "strictly increasing"),
+    (dict(idx=[0, 4, 13]), "out of range"),
+    (dict(idx=[-1, 4, 7]), "out of range"),
+    (dict(offs=[0, 0], idx=[]), "selects no entry"),
+    (dict(offs=[1, 3]), "offs[0]"),
+    (dict(widths_a=[2]), "widths"),
+    (dict(widths_a=[2, 0, 1]), "widths"),
+    (dict(widths_a=[2, 5000, 1]), "widths"),
+    (dict(prior_sd=0.0), "prior_sd"),
+    (dict(lik_sd=float("nan")), "lik_sd"),
+    (dict(precision=7), "precision"),
+    (dict(kind=4), "kind"),
+    (dict(n_rows=0), "n_rows"),
+    (dict(no_y=True), "x and y"),
+])
+def test_invalid_arguments_are_rejected_on_the_host(over, needle):
+    st, ctx, msg = _init(**over)
+    assert st == binding.HMC_EINVAL
+    assert not ctx.value
+    assert needle in msg, msg
+
+
+@needs_lib
+def test_null_descriptors_are_rejected():
+    lib = binding.load()
+    ctx = ctypes.c_void_p()
+    assert lib.hmc_init(ctypes.byref(ctx), None, None, None, 0, None) == binding.HMC_EINVAL
+    assert lib.hmc_init(None, None, None, None, 0, None) == binding.HMC_EINVAL
+
+
+@needs_lib
+def test_calls_on_a_null_engine_are_rejected():
+    lib = binding.load()
+    assert lib.hmc_sync(None) == binding.HMC_EINVAL
+    assert lib.hmc_grad(None, None, None) == binding.HMC_EINVAL
+    lib.hmc_destroy(None)
