@@ -14,6 +14,7 @@ L = 50, eps = 5e-4); --config selects another named workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -59,6 +60,19 @@ def algorithmic_flops(w, offs=None):
             nu, nq, p = w.u.shape[0], w.yq.shape[0], w.widths_a[-1]
             total += 3 * 2.0 * nu * nq * p
     return total
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy), or None
+    when the kernel source has changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    src = os.path.join(ROOT, "paper_2507_14652_amd", "csrc", "hmc_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256") == h else None
 
 
 def cpu_baseline(w, budget_s):
@@ -126,8 +140,9 @@ def main():
     dom_ms = ms[0]
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAK[DTYPE[w.precision]]
+    kname = "k_mlp_grad" if w.kind == "mlp" else "k_branch_grad"
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "k_mlp_grad" if w.kind == "mlp" else "k_branch_grad",
+            "traffic": recorded_traffic(kname, w.name), "kernel": kname,
             "kernel_ms": dom_ms, "flops_per_launch": flops}
 
     acc = float(stats["accepted"].mean())

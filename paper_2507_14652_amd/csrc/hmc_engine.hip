@@ -87,6 +87,7 @@ struct hmc_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_L = -1;
+    int dense_layers = 0;         // (chain, layer) pairs on the dense weight-gradient path
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     hmc_status fail(hmc_status s, const std::string& m) { err = m; return s; }
@@ -322,9 +323,11 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     GradArgs& g = x->ga;
     fill_plan(g.ta, x->A.w, prec, x->Ra);
     g.ta.seg0 = 0;
+    for (int l = 0; l < la; ++l) g.ta.fo[l] = x->A.lstart[l];
     if (x->kind == HMC_DEEPONET) {
         fill_plan(g.tb, x->B.w, prec, x->Rb);
         g.tb.seg0 = la;
+        for (int l = 0; l < lb; ++l) g.tb.fo[l] = x->B.lstart[l];
     }
 
     // Per-chain weight and bias layout.
@@ -482,6 +485,70 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             }
         }
     }
+    // Per layer: where its bias entries start, and whether its weight partials
+    // come from a dense tile product (selected entries picked through a
+    // position map) or from per-entry sums.  The dense product does work in
+    // proportion to in*out and the per-entry sums in proportion to the
+    // selected count, but its stores are scattered through the position map;
+    // measured on MI355X it is slower at every density of the named
+    // workloads, so per-entry sums are the default and HMC_DW=dense selects
+    // the dense product (for layers at or above the density threshold).
+    const int nlt = la + lb;
+    std::vector<int> bseg((size_t)x->C * std::max(nlt, 1)), dflag((size_t)x->C * std::max(nlt, 1));
+    const char* dwenv = std::getenv("HMC_DW");
+    const int kch = prec == HMC_BF16 ? 32 : 16;
+    const int thr = prec == HMC_BF16 ? 128 : 32;   // dense when density >= 1/thr
+    for (int c = 0; c < x->C; ++c) {
+        const long long o = x->offs[c], n = x->offs[c + 1] - o;
+        const int64_t* id = mask->idx + o;
+        for (int L = 0; L < nlt; ++L) {
+            const TowerPlan& tp = *lplan[L];
+            const int l = lidx[L];
+            const long long wend = lstart[L] + (long long)tp.w[l] * tp.w[l + 1];
+            const int b = (int)(std::lower_bound(id, id + n, (int64_t)wend) - id);
+            bseg[(size_t)c * nlt + L] = b;
+            const long long nw = b - seg[(size_t)c * nseg + L];
+            const int R = L < la ? x->Ra : x->Rb;
+            const bool dense = dwenv && !std::strcmp(dwenv, "dense") && nw > 0 && R % kch == 0 &&
+                               nw * thr >= (long long)tp.w[l] * tp.w[l + 1];
+            dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
+        }
+    }
+    // Position maps: chain-local entry index of every flat parameter (-1 if
+    // fixed); chains with the same mask share one map.
+    std::vector<long long> pos_off(x->C);
+    std::vector<int> pos_h;
+    std::vector<int> distinct;   // first chain of each distinct mask
+    for (int c = 0; c < x->C; ++c) {
+        const long long o = x->offs[c], n = x->offs[c + 1] - o;
+        int same = -1;
+        for (int d : distinct) {
+            const long long od = x->offs[d], nd = x->offs[d + 1] - od;
+            if (nd == n && std::equal(mask->idx + o, mask->idx + o + n, mask->idx + od)) { same = d; break; }
+        }
+        if (same >= 0) { pos_off[c] = pos_off[same]; continue; }
+        distinct.push_back(c);
+        pos_off[c] = (long long)pos_h.size();
+        pos_h.resize(pos_h.size() + (size_t)x->P, -1);
+        int* m = pos_h.data() + pos_off[c];
+        for (long long k = 0; k < n; ++k) m[mask->idx[o + k]] = (int)k;
+    }
+    int* bseg_d = (int*)x->dalloc(sizeof(int) * bseg.size());
+    int* dflag_d = (int*)x->dalloc(sizeof(int) * dflag.size());
+    int* pos_d = (int*)x->dalloc(sizeof(int) * pos_h.size());
+    long long* posoff_d = (long long*)x->dalloc(sizeof(long long) * x->C);
+    if (!bseg_d || !dflag_d || !pos_d || !posoff_d) return x->fail(HMC_ENOMEM, "device allocation of the position maps failed");
+    HMC_HIP(x, hipMemcpy(bseg_d, bseg.data(), sizeof(int) * bseg.size(), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(dflag_d, dflag.data(), sizeof(int) * dflag.size(), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(pos_d, pos_h.data(), sizeof(int) * pos_h.size(), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(posoff_d, pos_off.data(), sizeof(long long) * x->C, hipMemcpyHostToDevice));
+    g.bseg = bseg_d;
+    g.dflag = dflag_d;
+    g.nl_total = nlt;
+    g.pos = pos_d;
+    g.pos_off = posoff_d;
+    x->dense_layers = (int)std::count(dflag.begin(), dflag.end(), 1);
+
     long long* offs_d = (long long*)x->dalloc(sizeof(long long) * (x->C + 1));
     int* code_d = (int*)x->dalloc(sizeof(int) * x->nnz);
     int* dst_d = (int*)x->dalloc(sizeof(int) * 2 * x->nnz);

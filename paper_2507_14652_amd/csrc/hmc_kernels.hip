@@ -128,6 +128,7 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
     typedef typename PT<P>::Acc Acc;
     typedef typename PT<P>::Frag Frag;
     constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
+    constexpr int GK = 4 * KCH;              // K extent of one group of four chunks
     constexpr int RG = (R / 16) / NRB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
@@ -136,19 +137,54 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
     // land on rows 4g + v as well, so every epilogue sees the same layout.
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
     const int units = (Np >> 4) * RG;
-    for (int u = wave; u < units; u += NWAVE) {
+    const int my_units = units > wave ? (units - wave + NWAVE - 1) / NWAVE : 0;
+    const int ng = K / GK;                   // full groups; K % GK chunks follow per unit
+    const int rem = (K - ng * GK) / KCH;
+    // Weight fragments of the wave's whole (unit, group) stream are loaded one
+    // group ahead, so the L2 latency of group s+1 overlaps the MFMAs of group s.
+    auto wrow = [&](int ui) {
+        const int u = wave + ui * NWAVE;
+        return Wm + (size_t)((u / RG) * 16 + arow) * ldw + g * VEC;
+    };
+    Frag aA[4], aB[4];
+    const int steps = my_units * ng;
+    auto load_group = [&](Frag* a, int st) {
+        const T* wr = wrow(st / ng) + (st % ng) * GK;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
+    };
+    if (steps > 0) load_group(aA, 0);
+    int st = 0;
+    for (int ui = 0; ui < my_units; ++ui) {
+        const int u = wave + ui * NWAVE;
         const int nb = u / RG, rg = u - nb * RG;
+        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
         Acc acc[NRB];
 #pragma unroll
         for (int i = 0; i < NRB; ++i) acc[i] = Acc{};
-        const T* wr = Wm + (size_t)(nb * 16 + arow) * ldw + g * VEC;
-        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
-        for (int k0 = 0; k0 < K; k0 += KCH) {
-            const Frag a = *reinterpret_cast<const Frag*>(wr + k0);
+        for (int grp = 0; grp < ng; ++grp, ++st) {
+            // ping-pong between the two fragment buffers without dynamic indexing
+            Frag* cur = (st & 1) ? aB : aA;
+            Frag* nxt = (st & 1) ? aA : aB;
+            if (st + 1 < steps) load_group(nxt, st + 1);
 #pragma unroll
-            for (int i = 0; i < NRB; ++i) {
-                const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + k0);
-                mma(acc[i], a, b);
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int i = 0; i < NRB; ++i) {
+                    const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + grp * GK + q * KCH);
+                    mma(acc[i], cur[q], b);
+                }
+            }
+        }
+        if (rem) {
+            const T* wr = wrow(ui) + ng * GK;
+            for (int c = 0; c < rem; ++c) {
+                const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
+#pragma unroll
+                for (int i = 0; i < NRB; ++i) {
+                    const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
+                    mma(acc[i], a, b);
+                }
             }
         }
 #pragma unroll
@@ -324,6 +360,88 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
     }
 }
 
+// Dense weight-gradient tile, selected entries kept: for output rows i and
+// input columns j of a layer,
+//   dW[i][j] = sum_r delta[r][i] * a[r][j]
+// as an MFMA product whose K dimension runs over the tile rows; each entry
+// with a position in the chain's map goes to part[pos].  The operands sit
+// row-major in LDS, so each lane reads its K values (consecutive rows) one
+// scalar at a time; BI x BJ register blocking reuses every fragment across
+// BJ (or BI) products.  Requires R to be a multiple of the K chunk.
+template <int P, int R, int BI, int BJ>
+__device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
+                                               int lx, int out_w, int in_w, int NI, int NJ,
+                                               const int* __restrict__ pos, typename PT<P>::A* __restrict__ part) {
+    typedef typename PT<P>::A A;
+    typedef typename PT<P>::Acc Acc;
+    typedef typename PT<P>::Frag Frag;
+    constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
+    const int UI = (NI + BI - 1) / BI, UJ = (NJ + BJ - 1) / BJ;
+    const int imax = NI * 16 - 1, jmax = NJ * 16 - 1;
+    for (int u = wave; u < UI * UJ; u += NWAVE) {
+        const int ui = u / UJ, uj = u - ui * UJ;
+        Acc acc[BI][BJ];
+        int ic[BI], jc[BJ];
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi) {
+            ic[bi] = min((ui * BI + bi) * 16 + arow, imax);
+#pragma unroll
+            for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = Acc{};
+        }
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj) jc[bj] = min((uj * BJ + bj) * 16 + li, jmax);
+#pragma unroll
+        for (int k0 = 0; k0 < R; k0 += KCH) {
+            const int r0 = k0 + g * VEC;
+            Frag a[BI], b[BJ];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+#pragma unroll
+                for (int bi = 0; bi < BI; ++bi) a[bi][e] = D[(r0 + e) * ld + ic[bi]];
+#pragma unroll
+                for (int bj = 0; bj < BJ; ++bj) b[bj][e] = X[(r0 + e) * lx + jc[bj]];
+            }
+#pragma unroll
+            for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < BJ; ++bj) mma(acc[bi][bj], a[bi], b[bj]);
+        }
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < BJ; ++bj) {
+                const int j = (uj * BJ + bj) * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = (ui * BI + bi) * 16 + 4 * g + v;
+                    if (i < out_w && j < in_w) {
+                        const int k = pos[(size_t)i * in_w + j];
+                        if (k >= 0) part[k] = (A)acc[bi][bj][v];
+                    }
+                }
+            }
+    }
+}
+
+template <int P, int R>
+__device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
+                                         int out_w, int in_w, int NI, int NJ, const int* pos,
+                                         typename PT<P>::A* part) {
+    if constexpr (R % PT<P>::KCH == 0) {
+        if constexpr (P != 0) {
+            if ((NI / 4) * (NJ / 4) >= NWAVE) {
+                dw_dense_units<P, R, 4, 4>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
+                return;
+            }
+        }
+        if ((NI / 2) * (NJ / 2) >= NWAVE) dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
+        else dw_dense_units<P, R, 1, 1>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
+    }
+}
+
 template <int P, int R>
 __device__ __forceinline__ void tower_hidden_forward(const TowerPlan& tp, const typename PT<P>::T* W,
                                                      const typename PT<P>::A* B, typename PT<P>::T* sm) {
@@ -349,8 +467,16 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     int lowest = tp.nl;
     for (int l = 0; l < tp.nl; ++l)
         if (seg[l + 1] > seg[l]) { lowest = l; break; }
+    const int* bseg = a.bseg + (size_t)c * a.nl_total + tp.seg0;
+    const int* dflag = a.dflag + (size_t)c * a.nl_total + tp.seg0;
     for (int l = tp.nl - 1; l >= lowest; --l) {
-        dw_partials<P, R>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+        if (dflag[l]) {
+            dw_dense<P, R>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
+                           tp.wp[l + 1] >> 4, tp.wp[l] >> 4, a.pos + a.pos_off[c] + tp.fo[l], part);
+            dw_partials<P, R>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+        } else {
+            dw_partials<P, R>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+        }
         if (l > lowest) {
             __syncthreads();
             EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};
@@ -510,8 +636,16 @@ __global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode) {
     const int* seg = s.seg + (size_t)c * s.nseg;
     const int nt = (k >= seg[s.seg_trunk_lo] && k < seg[s.seg_trunk_hi]) ? s.tiles_b : s.tiles_a;
     const A* pp = reinterpret_cast<const A*>(s.part) + s.tmax * o + k;
-    A acc = (A)0;
-    for (int t = 0; t < nt; ++t) acc += pp[(size_t)t * n];
+    // eight independent partial sums (tiles t = j mod 8), combined in a fixed
+    // order: the loads overlap and the result does not depend on timing
+    A q[8] = {(A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0};
+    int t = 0;
+    for (; t + 8 <= nt; t += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] += pp[(size_t)(t + j) * n];
+    }
+    for (int j = 0; t < nt; ++t, ++j) q[j] += pp[(size_t)t * n];
+    const A acc = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
     S* th = reinterpret_cast<S*>(s.theta) + o;
     S x = th[k];
     const S g = (S)acc + x * (S)s.inv_prior_var;

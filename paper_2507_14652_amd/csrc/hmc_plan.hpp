@@ -23,6 +23,7 @@ struct TowerPlan {
     long long wo[HMC_MAXL];     // offset of W_l in the per-chain weight buffer
     long long wto[HMC_MAXL];    // offset of W_l^T
     long long bo[HMC_MAXL];     // offset of b_l in the per-chain bias buffer
+    long long fo[HMC_MAXL];     // flat parameter index of W_l[0][0]
     int seg0;                   // first layer of this tower in the segment table
 };
 
@@ -48,6 +49,11 @@ struct GradArgs {
     const int* ecode;           // [nnz] (i << 16) | j, j = 0xFFFF for a bias
     const int* seg;             // [C][nseg] chain-local start of each layer's entries
     int nseg;
+    const int* bseg;            // [C][nl_total] chain-local start of each layer's bias entries
+    const int* dflag;           // [C][nl_total] 1: weight partials by a dense tile product
+    int nl_total;
+    const int* pos;             // chain-local entry index of each flat parameter, -1 if fixed
+    const long long* pos_off;   // [C] offset of each chain's map in pos (equal masks share one)
     void* part;                 // per-tile gradient partials, A
     long long tmax;             // tiles per chain in the partial layout
     double* ulik;               // [C][tiles_a] likelihood partials

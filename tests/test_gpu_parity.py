@@ -151,3 +151,50 @@ def test_fp64_chain_matches_oracle_chain():
     np.testing.assert_allclose(stats["log_u"][:, 0], [st["log_u"] for st in rstats], rtol=1e-15)
     np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
     s.close()
+
+
+@pytest.mark.parametrize("path", ["dense", "gather"])
+@pytest.mark.parametrize("name,kw,prec", [
+    ("regress2d_fp32", dict(n_rows=1000, n_chains=2), "fp64"),
+    ("regress2d_fp32", dict(n_rows=1000, n_chains=2), "fp32"),
+    ("uneven_mlp_bf16", dict(n_rows=200, n_chains=3), "fp32"),
+    ("antideriv_deeponet_bf16", dict(n_u=150, n_q=37, n_chains=2), "fp32"),
+])
+def test_weight_gradient_paths_match_oracle(name, kw, prec, path, monkeypatch):
+    """Both ways of forming the selected weight-gradient partials (a dense
+    tile product read through the position map, or per-entry sums) give the
+    oracle's gradient."""
+    monkeypatch.setenv("HMC_DW", path)
+    w = workloads.make(name, **kw)
+    s = _sampler(w, precision=prec)
+    U, g = s.grad()
+    g = g.double().cpu().numpy()
+    for c in range(w.n_chains):
+        post = on.posterior_for_chain(w, c)
+        Ur, gr = post.potential_and_grad(_state0(w, c, prec))
+        sl = slice(w.offs[c], w.offs[c + 1])
+        eg = _rel(g[sl], gr)
+        print(f"{path} {name} {prec} chain {c}: g rel {eg:.2e}")
+        assert eg <= REL[prec]
+    s.close()
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("uneven_mlp_bf16", dict(n_rows=200, n_chains=3)),
+    ("antideriv_deeponet_bf16", dict(n_u=150, n_q=37, n_chains=2)),
+])
+def test_bf16_weight_gradient_paths_agree(name, kw, monkeypatch):
+    """In BF16 mode the two paths sum the same bf16 products in FP32 in a
+    different order: they agree to FP32 rounding of the sums."""
+    out = {}
+    monkeypatch.setenv("HMC_ROWS_A", "32")   # the bf16 dense product needs 32-row tiles
+    monkeypatch.setenv("HMC_ROWS_B", "32")
+    for path in ("dense", "gather"):
+        monkeypatch.setenv("HMC_DW", path)
+        w = workloads.make(name, **kw)
+        s = _sampler(w, precision="bf16")
+        out[path] = s.grad()[1].double().cpu().numpy()
+        s.close()
+    e = _rel(out["dense"], out["gather"])
+    print(f"bf16 {name}: dense vs gather {e:.2e}")
+    assert 0 < e <= 1e-5   # nonzero: the two paths really differ in summation order
