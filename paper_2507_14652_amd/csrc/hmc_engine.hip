@@ -79,6 +79,11 @@ struct hmc_ctx {
     size_t lds_a = 0, lds_b = 0;
     GradArgs ga{};
     StateArgs sa{};
+    // BF16 engines: FP32 energy pass over an FP32 shadow of the weights
+    bool energy32 = false;
+    GradArgs ga32{};
+    int Ra32 = 0, Rb32 = 0, tiles_a32 = 0, tiles_b32 = 0, grid_a32 = 0, grid_b32 = 0;
+    size_t lds_a32 = 0, lds_b32 = 0;
     std::vector<void*> allocs;
     long long dev_bytes = 0;
     std::vector<int> active_h;
@@ -212,6 +217,31 @@ void fill_plan(TowerPlan& tp, const std::vector<int>& w, int prec, int R) {
     }
 }
 
+// Plan of the FP32 energy pass of a BF16 engine: the same padded widths and
+// weight offsets as the BF16 plan (so one scatter serves both copies), FP32
+// LDS strides, and two activation slabs used alternately (forward only).
+void fill_plan_energy(TowerPlan& tp, const TowerPlan& src, int R) {
+    tp = src;
+    int mx = 0;
+    for (int l = 0; l <= src.nl; ++l) {
+        tp.ls[l] = src.wp[l] + 4;
+        mx = std::max(mx, tp.ls[l]);
+    }
+    for (int l = 0; l <= src.nl; ++l) tp.lo[l] = (l % 2) * R * mx;
+}
+
+size_t energy_lds(const TowerPlan& src, int R) {
+    int mx = 0;
+    for (int l = 0; l <= src.nl; ++l) mx = std::max(mx, src.wp[l] + 4);
+    return ((size_t)2 * R * mx * 4 + 15) / 16 * 16;
+}
+
+int pick_rows_energy(const TowerPlan& src) {
+    for (int R : {64, 32, 16})
+        if (energy_lds(src, R) + 64 <= g_lds_cap) return R;
+    return 0;
+}
+
 // Largest row tile whose LDS footprint fits, shrunk while the grid would
 // leave most compute units idle.  HMC_ROWS_A / HMC_ROWS_B override it.
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, long long rows, int chains,
@@ -243,10 +273,24 @@ hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
 
 int update_grid(const hmc_ctx* x) { return (x->max_n + 255) / 256; }
 
+// FP32 energy pass of BF16 engines: the likelihood partials that define U in
+// the Hamiltonian, at the current positions.
+hmc_status launch_energy(hmc_ctx* x, hipStream_t s) {
+    if (!x->energy32) return HMC_OK;
+    if (x->kind == HMC_MLP) {
+        HMC_HIP(x, hmc_launch_mlp_energy(x->Ra32, x->ga32, x->grid_a32, x->lds_a32, s));
+    } else {
+        HMC_HIP(x, hmc_launch_trunk_fwd(HMC_FP32, x->Rb32, x->ga32, x->grid_b32, x->lds_b32, s));
+        HMC_HIP(x, hmc_launch_branch_energy(x->Ra32, x->ga32, x->grid_a32, x->lds_a32, s));
+    }
+    return HMC_OK;
+}
+
 // Gradient and U at the current positions (no kick).
 hmc_status launch_refresh(hmc_ctx* x, hipStream_t s) {
     HMC_TRY(launch_grad(x, s));
     HMC_HIP(x, hmc_launch_update(x->prec, x->sa, UPD_GRAD, update_grid(x), s));
+    HMC_TRY(launch_energy(x, s));
     HMC_HIP(x, hmc_launch_traj_end(x->prec, x->sa, END_ENERGY, s));
     return HMC_OK;
 }
@@ -260,7 +304,7 @@ hmc_status launch_leapfrog(hmc_ctx* x, const StateArgs& sa, int L, hipStream_t s
         HMC_TRY(launch_grad(x, s));
         HMC_HIP(x, hmc_launch_update(x->prec, sa, t < L ? UPD_KICK_DRIFT : UPD_HALF_KICK, update_grid(x), s));
     }
-    return HMC_OK;
+    return launch_energy(x, s);
 }
 
 hmc_status set_eps_active(hmc_ctx* x, const std::vector<double>& eps, const std::vector<int>& active) {
@@ -349,23 +393,23 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
 
     // Dense weights from theta0 (identical for every chain before the scatter).
     std::vector<unsigned char> wh((size_t)g.wstride * ts, 0), bh((size_t)g.bstride * as, 0);
-    auto fill_tower = [&](const TowerPlan& tp, const TowerHost& th) {
+    auto fill_tower = [&](std::vector<unsigned char>& buf, int bprec, const TowerPlan& tp, const TowerHost& th) {
         for (int l = 0; l < tp.nl; ++l) {
             const int in = tp.w[l], out = tp.w[l + 1];
             const long long f0 = th.lstart[l];
             for (int i = 0; i < out; ++i) {
                 for (int j = 0; j < in; ++j) {
                     const double v = net->theta0[f0 + (long long)i * in + j];
-                    put_t(wh, prec, (size_t)(tp.wo[l] + (long long)i * tp.wp[l] + j), v);
-                    put_t(wh, prec, (size_t)(tp.wto[l] + (long long)j * tp.wp[l + 1] + i), v);
+                    put_t(buf, bprec, (size_t)(tp.wo[l] + (long long)i * tp.wp[l] + j), v);
+                    put_t(buf, bprec, (size_t)(tp.wto[l] + (long long)j * tp.wp[l + 1] + i), v);
                 }
                 put_a(bh, prec, (size_t)(tp.bo[l] + i), net->theta0[f0 + (long long)out * in + i]);
             }
         }
     };
-    fill_tower(g.ta, x->A);
+    fill_tower(wh, prec, g.ta, x->A);
     if (x->kind == HMC_DEEPONET) {
-        fill_tower(g.tb, x->B);
+        fill_tower(wh, prec, g.tb, x->B);
         put_a(bh, prec, (size_t)g.b0_off, net->theta0[x->P - 1]);
     }
     void* wd = x->dalloc((size_t)x->C * g.wstride * ts);
@@ -571,6 +615,64 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.ulik = (double*)x->dalloc(sizeof(double) * x->C * x->tiles_a);
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
 
+    // BF16 engines: FP32 shadow for the energy pass (same offsets as wbuf).
+    // Built after every field of the BF16 arguments is final, since the
+    // energy arguments start as a copy of them.
+    void* w32 = nullptr;
+    if (prec == HMC_BF16) {
+        x->energy32 = true;
+        GradArgs& e = x->ga32;
+        e = g;
+        x->Ra32 = pick_rows_energy(g.ta);
+        if (!x->Ra32) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS for the FP32 energy pass");
+        fill_plan_energy(e.ta, g.ta, x->Ra32);
+        x->tiles_a32 = (int)((rows_a + x->Ra32 - 1) / x->Ra32);
+        x->grid_a32 = roundup(x->C * x->tiles_a32, 8);
+        x->lds_a32 = energy_lds(g.ta, x->Ra32);
+        e.red_off = (int)x->lds_a32;
+        x->lds_a32 += 64;
+        std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
+        fill_tower(w32h, HMC_FP32, g.ta, x->A);
+        if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
+        w32 = x->dalloc((size_t)x->C * g.wstride * 4);
+        if (!w32) return x->fail(HMC_ENOMEM, "device allocation of the FP32 weight shadow failed");
+        for (int c = 0; c < x->C; ++c)
+            HMC_HIP(x, hipMemcpy((char*)w32 + (size_t)c * g.wstride * 4, w32h.data(), w32h.size(), hipMemcpyHostToDevice));
+        e.wbuf = w32;
+        auto upload32 = [&](const double* src, long long rows, int w, int wp, int R, int tiles) -> void* {
+            std::vector<unsigned char> h((size_t)tiles * R * wp * 4, 0);
+            for (long long r = 0; r < rows; ++r)
+                for (int j = 0; j < w; ++j) put_t(h, HMC_FP32, (size_t)(r * wp + j), src[r * w + j]);
+            void* d = x->dalloc(h.size());
+            if (d && hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+            return d;
+        };
+        e.tiles_a = x->tiles_a32;
+        e.ulik = (double*)x->dalloc(sizeof(double) * x->C * x->tiles_a32);
+        if (x->kind == HMC_MLP) {
+            e.xa = upload32(data->x, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
+        } else {
+            e.xa = upload32(data->u, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
+            x->Rb32 = pick_rows_energy(g.tb);
+            if (!x->Rb32) return x->fail(HMC_EUNSUPPORTED, "trunk does not fit in LDS for the FP32 energy pass");
+            fill_plan_energy(e.tb, g.tb, x->Rb32);
+            x->tiles_b32 = (int)((rows_b + x->Rb32 - 1) / x->Rb32);
+            x->grid_b32 = roundup(x->C * x->tiles_b32, 8);
+            x->lds_b32 = energy_lds(g.tb, x->Rb32) + 64;
+            e.tiles_b = x->tiles_b32;
+            e.xb = upload32(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);
+            const int pp = g.ta.wp[la];
+            e.nq_rows = std::max(nq_pad, x->tiles_b32 * x->Rb32);
+            e.tm_stride = (long long)e.nq_rows * pp;
+            e.tm = x->dalloc((size_t)x->C * e.tm_stride * 4);
+            e.tt = x->dalloc((size_t)x->C * e.tm_stride * 4);
+            if (!e.xb || !e.tm || !e.tt) return x->fail(HMC_ENOMEM, "device allocation of the energy pass failed");
+        }
+        if (!e.xa || !e.ulik) return x->fail(HMC_ENOMEM, "device allocation of the energy pass failed");
+        HMC_HIP(x, hmc_set_lds_limit(HMC_FP32, x->Ra32, g_lds_cap));
+        if (x->Rb32) HMC_HIP(x, hmc_set_lds_limit(HMC_FP32, x->Rb32, g_lds_cap));
+    }
+
     // Chain state.
     StateArgs& s = x->sa;
     s.n_chains = x->C;
@@ -584,7 +686,9 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.tiles_b = x->tiles_b;
     s.tmax = g.tmax;
     s.part = g.part;
-    s.ulik = g.ulik;
+    s.ulik = x->energy32 ? x->ga32.ulik : g.ulik;
+    s.ulik_tiles = x->energy32 ? x->tiles_a32 : x->tiles_a;
+    s.wbuf32 = w32;
     s.dst = dst_d;
     s.wbuf = wd;
     s.wstride = g.wstride;

@@ -274,14 +274,14 @@ template <int P> struct EpiMlpHead {
 // written to global memory for the trunk adjoint (zero for padded rows).
 template <int P> struct EpiBranchOut {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
-    const A* bias; T* out; int ld; T* bt; int bt_ld; int col0; int nvalid;
+    const A* bias; T* out; int ld; T* bt; int bt_ld; int col0; int nvalid; bool store;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
         typename PT<P>::O4 o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const T tv = (T)((A)acc[v] + bias[n0 + v]);
             o[v] = tv;
-            bt[(size_t)(n0 + v) * bt_ld + col0 + r] = (r < nvalid) ? tv : (T)0;
+            if (store) bt[(size_t)(n0 + v) * bt_ld + col0 + r] = (r < nvalid) ? tv : (T)0;
         }
         *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
     }
@@ -312,7 +312,7 @@ template <int P> struct EpiTrunkOut {
 template <int P> struct EpiCombine {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     T* dg; int dg_ld; T* dgt; int dgt_ld; int col0;
-    const double* v; int nq; int nvalid; int row0; double b0; double iv;
+    const double* v; int nq; int nvalid; int row0; double b0; double iv; bool store;
     double sq; double sdg;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) {
         typename PT<P>::O4 o;
@@ -328,9 +328,9 @@ template <int P> struct EpiCombine {
                 d = (T)(A)dd;
             }
             o[w] = d;
-            dgt[(size_t)q * dgt_ld + col0 + r] = d;
+            if (store) dgt[(size_t)q * dgt_ld + col0 + r] = d;
         }
-        *reinterpret_cast<typename PT<P>::O4*>(dg + r * dg_ld + n0) = o;
+        if (store) *reinterpret_cast<typename PT<P>::O4*>(dg + r * dg_ld + n0) = o;
     }
 };
 
@@ -488,7 +488,9 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
 
 // ---------------------------------------------------------------------------
 // MLP: forward, head and adjoint of one (chain, row tile).
-template <int P, int R>
+// FWD = true: forward pass and likelihood partials only (the energy pass),
+// with activation slabs that may alias (ping-pong plans).
+template <int P, int R, bool FWD>
 __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -509,7 +511,7 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
     const double sq = block_sum(h.sq, red);
     if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
-    tower_backward<P, R>(a, tp, c, t, W, sm);
+    if constexpr (!FWD) tower_backward<P, R>(a, tp, c, t, W, sm);
 }
 
 // DeepONet trunk forward: T = trunk(y_q) for one (chain, query tile).
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_fwd(const GradArgs a) {
 
 // DeepONet branch tile: branch forward, combination with the trunk features,
 // FP64 head, adjoint of the branch output, branch adjoint pass.
-template <int P, int R>
+template <int P, int R, bool FWD>
 __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -555,14 +557,18 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     const int pp = tp.wp[L + 1];
     const int nvalid = a.n_rows_a - t * R;
     EpiBranchOut<P> eo{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1],
-                       reinterpret_cast<T*>(a.btr) + c * a.bt_stride, a.nu_cols, t * R, nvalid};
+                       reinterpret_cast<T*>(a.btr) + c * a.bt_stride, a.nu_cols, t * R, nvalid, !FWD};
     gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], pp, sm + tp.lo[L], tp.ls[L], eo);
     __syncthreads();
     EpiCombine<P> ec{sm + a.dg_off, a.dg_ld, reinterpret_cast<T*>(a.dgt) + c * a.dgt_stride, a.nu_cols, t * R,
-                     a.target, a.nq, nvalid, t * R, (double)B[a.b0_off], a.inv_lik_var, 0.0, 0.0};
+                     a.target, a.nq, nvalid, t * R, (double)B[a.b0_off], a.inv_lik_var, !FWD, 0.0, 0.0};
     gemm<P, R>(reinterpret_cast<const T*>(a.tm) + c * a.tm_stride, pp, pp, a.nq_pad, sm + tp.lo[L + 1],
                tp.ls[L + 1], ec);
     const double sq = block_sum(ec.sq, red);
+    if constexpr (FWD) {
+        if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
+        return;
+    }
     const double sdg = block_sum(ec.sdg, red);
     if (threadIdx.x == 0) {
         a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
@@ -617,6 +623,11 @@ __device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, 
         T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;
         W[d0] = (T)x;
         W[d1] = (T)x;
+        if (s.wbuf32) {   // FP32 shadow of the weights for the energy pass
+            float* W32 = reinterpret_cast<float*>(s.wbuf32) + c * s.wstride;
+            W32[d0] = (float)x;
+            W32[d1] = (float)x;
+        }
     } else {
         reinterpret_cast<A*>(s.bbuf)[c * s.bstride + (-d0 - 1)] = (A)x;
     }
@@ -777,7 +788,7 @@ __global__ __launch_bounds__(256) void k_traj_end(const StateArgs s, int mode) {
     pri = 0.5 * s.inv_prior_var * block_sum(pri, red);
     kin = 0.5 * block_sum(kin, red);
     double ul = 0.0;
-    for (int t = 0; t < s.tiles_a; ++t) ul += s.ulik[(size_t)c * s.tiles_a + t];
+    for (int t = 0; t < s.ulik_tiles; ++t) ul += s.ulik[(size_t)c * s.ulik_tiles + t];
     const double U1 = ul + pri;
     if (mode == END_ENERGY) {
         if (threadIdx.x == 0) s.U[c] = U1;
@@ -866,10 +877,15 @@ __global__ __launch_bounds__(256) void k_scatter_all(const StateArgs s) {
 template <int P, int R>
 hipError_t set_lds(size_t lds) {
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-    return hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if constexpr (P == 1) {
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_branch_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -898,11 +914,11 @@ hipError_t hmc_set_lds_limit(int P, int R, size_t lds) {
 }
 
 #define HMC_TILE_CALL_k_mlp_grad(p, r) \
-    hipLaunchKernelGGL((k_mlp_grad<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_mlp_grad<p, r, false>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_trunk_fwd(p, r) \
     hipLaunchKernelGGL((k_trunk_fwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_branch_grad(p, r) \
-    hipLaunchKernelGGL((k_branch_grad<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_branch_grad<p, r, false>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_trunk_bwd(p, r) \
     hipLaunchKernelGGL((k_trunk_bwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
 
@@ -917,6 +933,26 @@ hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, siz
 }
 hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_trunk_bwd)
+}
+
+// FP32 energy pass (forward and likelihood partials only).
+hipError_t hmc_launch_mlp_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    switch (R) {
+        case 16: hipLaunchKernelGGL((k_mlp_grad<1, 16, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_mlp_grad<1, 32, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_mlp_grad<1, 64, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t hmc_launch_branch_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    switch (R) {
+        case 16: hipLaunchKernelGGL((k_branch_grad<1, 16, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_branch_grad<1, 32, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_branch_grad<1, 64, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st) {

@@ -10,6 +10,8 @@ hipError_t hmc_launch_mlp_grad(int P, int R, const GradArgs& a, int grid, size_t
 hipError_t hmc_launch_trunk_fwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_branch_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
 hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);

@@ -83,7 +83,8 @@ struct StateArgs {
     int tiles_a, tiles_b;
     long long tmax;
     const void* part;
-    const double* ulik;
+    const double* ulik;         // likelihood partials that define U (energy pass)
+    int ulik_tiles;
     void* theta;                // S [nnz]
     void* mom;                  // S [nnz]
     void* grad;                 // S [nnz]
@@ -95,6 +96,7 @@ struct StateArgs {
     const int* dst;             // [2 * nnz] scatter destinations
     void* wbuf;
     long long wstride;
+    void* wbuf32;               // FP32 shadow of wbuf (same offsets) or null
     void* bbuf;
     long long bstride;
     const double* eps;          // [C]

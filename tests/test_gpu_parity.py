@@ -82,7 +82,8 @@ def test_bf16_gradient_within_measured_bound(name, kw):
         sl = slice(w.offs[c], w.offs[c + 1])
         eU, eg = abs(U[c] - Ur) / abs(Ur), _rel(g[sl], gr)
         print(f"bf16 {name} chain {c}: U rel {eU:.2e}  g rel {eg:.2e}")
-        assert eU <= BF16_GRAD_BOUND and eg <= BF16_GRAD_BOUND
+        # U comes from the FP32 energy pass, the gradient from BF16 products
+        assert eU <= 1e-5 and eg <= BF16_GRAD_BOUND
     s.close()
 
 
