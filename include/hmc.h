@@ -142,6 +142,8 @@ typedef struct {
     int32_t tiles_a;
     int32_t tiles_b;
     int64_t device_bytes;     /* device memory held by the engine            */
+    int32_t threads_a;        /* threads per workgroup of the MLP / branch   */
+    int32_t threads_b;        /* ... and of the trunk tile kernels           */
 } hmc_info_t;
 
 /* Creates an engine: validates, uploads data and parameters, and evaluates

@@ -77,6 +77,11 @@ struct hmc_ctx {
     int Ra = 0, Rb = 0, tiles_a = 0, tiles_b = 0;
     int grid_a = 0, grid_b = 0;
     size_t lds_a = 0, lds_b = 0;
+    int nt_a = 256, nt_b = 256, nt_a32 = 256, nt_b32 = 256;   // threads per workgroup
+    // resident MLP kernel (weights in LDS, several tiles per workgroup)
+    bool resident = false;
+    int kpt = 0, groups = 0, grid_res = 0;
+    size_t lds_res = 0;
     GradArgs ga{};
     StateArgs sa{};
     // BF16 engines: FP32 energy pass over an FP32 shadow of the weights
@@ -198,6 +203,19 @@ hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hm
 
 // ----------------------------------------------------------------- planning
 
+// Threads per workgroup of a tile kernel.  A workgroup whose LDS leaves room
+// for a second one on the CU runs with 4 waves (two workgroups per CU hide
+// each other's barriers); one that holds the CU's LDS alone runs with 8 waves
+// so that the CU still has 8 waves in flight.  HMC_THREADS (256 or 512)
+// overrides the choice.
+int pick_threads(size_t lds) {
+    if (const char* s = std::getenv("HMC_THREADS")) {
+        const int t = std::atoi(s);
+        if (t == 256 || t == 512) return t;
+    }
+    return 2 * lds <= g_lds_cap ? 256 : 512;
+}
+
 size_t tower_lds(const std::vector<int>& w, int prec, int R) {
     size_t e = 0;
     for (int x : w) e += (size_t)R * (roundup(x, pad_of(prec)) + lpad_of(prec));
@@ -261,12 +279,14 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, long lo
 
 hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
     const int P = x->prec;
-    if (x->kind == HMC_MLP) {
-        HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, s));
+    if (x->resident) {
+        HMC_HIP(x, hmc_launch_mlp_res(P, x->Ra, x->kpt, x->ga, x->grid_res, x->lds_res, s));
+    } else if (x->kind == HMC_MLP) {
+        HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, s));
     } else {
-        HMC_HIP(x, hmc_launch_trunk_fwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, s));
-        HMC_HIP(x, hmc_launch_branch_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, s));
-        HMC_HIP(x, hmc_launch_trunk_bwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, s));
+        HMC_HIP(x, hmc_launch_trunk_fwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, s));
+        HMC_HIP(x, hmc_launch_branch_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, s));
+        HMC_HIP(x, hmc_launch_trunk_bwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, s));
     }
     return HMC_OK;
 }
@@ -278,10 +298,10 @@ int update_grid(const hmc_ctx* x) { return (x->max_n + 255) / 256; }
 hmc_status launch_energy(hmc_ctx* x, hipStream_t s) {
     if (!x->energy32) return HMC_OK;
     if (x->kind == HMC_MLP) {
-        HMC_HIP(x, hmc_launch_mlp_energy(x->Ra32, x->ga32, x->grid_a32, x->lds_a32, s));
+        HMC_HIP(x, hmc_launch_mlp_energy(x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
     } else {
-        HMC_HIP(x, hmc_launch_trunk_fwd(HMC_FP32, x->Rb32, x->ga32, x->grid_b32, x->lds_b32, s));
-        HMC_HIP(x, hmc_launch_branch_energy(x->Ra32, x->ga32, x->grid_a32, x->lds_a32, s));
+        HMC_HIP(x, hmc_launch_trunk_fwd(HMC_FP32, x->Rb32, x->nt_b32, x->ga32, x->grid_b32, x->lds_b32, s));
+        HMC_HIP(x, hmc_launch_branch_energy(x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
     }
     return HMC_OK;
 }
@@ -480,9 +500,11 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // The per-kernel limit is set to the device capacity (not this engine's
     // size) so that engines of different shapes in one process coexist.
     HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
+    x->nt_a = pick_threads(x->lds_a);
     if (x->kind == HMC_DEEPONET) {
         x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
         HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
+        x->nt_b = pick_threads(x->lds_b);
     }
 
     // Mask tables: entry codes, per-layer segments, scatter destinations.
@@ -529,6 +551,44 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             }
         }
     }
+    // Resident MLP kernel (HMC_RESIDENT=1): the padded weights (rows padded by
+    // 16 bytes) and the activation slabs fit in LDS, and every chain has at
+    // most 8 selected entries per thread.  Tiles per workgroup are chosen so
+    // that the grid is about one workgroup per compute unit.  Measured on the
+    // FP32 MLP workload it is slower than one tile per workgroup (the tiles of
+    // a workgroup run one after another at one workgroup per compute unit), so
+    // it is opt-in.
+    if (x->kind == HMC_MLP && x->max_n <= 8 * HMC_NT && std::getenv("HMC_RESIDENT") &&
+        !std::strcmp(std::getenv("HMC_RESIDENT"), "1")) {
+        const int E = (int)(16 / ts);
+        long long wl = 0;
+        TowerPlan& tp = g.ta;
+        for (int l = 0; l < tp.nl; ++l) {
+            tp.lwo[l] = (int)wl;
+            wl += (long long)tp.wp[l + 1] * (tp.wp[l] + E);
+            tp.lwto[l] = (int)wl;
+            wl += (long long)tp.wp[l] * (tp.wp[l + 1] + E);
+        }
+        const size_t acts = (tower_lds(x->A.w, prec, x->Ra) + 15) / 16 * 16;
+        const size_t need = acts + (size_t)wl * ts + 64;
+        if (need <= g_lds_cap) {
+            int cus = 0;
+            HMC_HIP(x, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device));
+            if (cus <= 0) cus = 256;
+            const long long total = (long long)x->C * x->tiles_a;
+            const int tpw = (int)std::max(1ll, (total + cus - 1) / cus);
+            x->resident = true;
+            x->kpt = x->max_n <= 4 * HMC_NT ? 4 : 8;
+            x->groups = (x->tiles_a + tpw - 1) / tpw;
+            x->grid_res = roundup(x->C * x->groups, 8);
+            g.tpw = tpw;
+            g.groups = x->groups;
+            g.w_lds_off = (int)(acts / ts);
+            g.red_off = (int)(acts + (size_t)wl * ts);
+            x->lds_res = need;
+        }
+    }
+
     // Per layer: where its bias entries start, and whether its weight partials
     // come from a dense tile product (selected entries picked through a
     // position map) or from per-entry sums.  The dense product does work in
@@ -610,9 +670,9 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.ecode = code_d;
     g.seg = seg_d;
     g.nseg = nseg;
-    g.tmax = std::max(x->tiles_a, x->tiles_b);
+    g.tmax = x->resident ? x->groups : std::max(x->tiles_a, x->tiles_b);
     g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
-    g.ulik = (double*)x->dalloc(sizeof(double) * x->C * x->tiles_a);
+    g.ulik = (double*)x->dalloc(sizeof(double) * x->C * (x->resident ? x->groups : x->tiles_a));
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
 
     // BF16 engines: FP32 shadow for the energy pass (same offsets as wbuf).
@@ -631,6 +691,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->lds_a32 = energy_lds(g.ta, x->Ra32);
         e.red_off = (int)x->lds_a32;
         x->lds_a32 += 64;
+        x->nt_a32 = pick_threads(x->lds_a32);
         std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
         fill_tower(w32h, HMC_FP32, g.ta, x->A);
         if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
@@ -659,6 +720,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             x->tiles_b32 = (int)((rows_b + x->Rb32 - 1) / x->Rb32);
             x->grid_b32 = roundup(x->C * x->tiles_b32, 8);
             x->lds_b32 = energy_lds(g.tb, x->Rb32) + 64;
+            x->nt_b32 = pick_threads(x->lds_b32);
             e.tiles_b = x->tiles_b32;
             e.xb = upload32(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);
             const int pp = g.ta.wp[la];
@@ -682,12 +744,12 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.nseg = nseg;
     s.seg_trunk_lo = la;
     s.seg_trunk_hi = la + lb;
-    s.tiles_a = x->tiles_a;
+    s.tiles_a = x->resident ? x->groups : x->tiles_a;   // partials per chain and tower
     s.tiles_b = x->tiles_b;
     s.tmax = g.tmax;
     s.part = g.part;
     s.ulik = x->energy32 ? x->ga32.ulik : g.ulik;
-    s.ulik_tiles = x->energy32 ? x->tiles_a32 : x->tiles_a;
+    s.ulik_tiles = x->energy32 ? x->tiles_a32 : (x->resident ? x->groups : x->tiles_a);
     s.wbuf32 = w32;
     s.dst = dst_d;
     s.wbuf = wd;
@@ -986,6 +1048,8 @@ hmc_status hmc_get_info(const hmc_ctx* x, hmc_info_t* info) {
     info->tiles_a = x->tiles_a;
     info->tiles_b = x->tiles_b;
     info->device_bytes = x->dev_bytes;
+    info->threads_a = x->resident ? HMC_NT : x->nt_a;
+    info->threads_b = x->kind == HMC_DEEPONET ? x->nt_b : 0;
     return HMC_OK;
 }
 
@@ -1008,11 +1072,11 @@ hmc_status hmc_time_kernels(hmc_ctx* x, int32_t reps, double* ms) {
         return HMC_OK;
     };
     if (x->kind == HMC_MLP) {
-        HMC_TRY(timed(0, [&] { return x->hip(hmc_launch_mlp_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, x->stream), "mlp_grad"); }));
+        HMC_TRY(timed(0, [&] { return launch_grad(x, x->stream); }));
     } else {
-        HMC_TRY(timed(1, [&] { return x->hip(hmc_launch_trunk_fwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_fwd"); }));
-        HMC_TRY(timed(0, [&] { return x->hip(hmc_launch_branch_grad(P, x->Ra, x->ga, x->grid_a, x->lds_a, x->stream), "branch_grad"); }));
-        HMC_TRY(timed(2, [&] { return x->hip(hmc_launch_trunk_bwd(P, x->Rb, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_bwd"); }));
+        HMC_TRY(timed(1, [&] { return x->hip(hmc_launch_trunk_fwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_fwd"); }));
+        HMC_TRY(timed(0, [&] { return x->hip(hmc_launch_branch_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, x->stream), "branch_grad"); }));
+        HMC_TRY(timed(2, [&] { return x->hip(hmc_launch_trunk_bwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_bwd"); }));
     }
     HMC_TRY(timed(3, [&] { return x->hip(hmc_launch_update(P, x->sa, UPD_GRAD, update_grid(x), x->stream), "update"); }));
     // leave U consistent with the gradient just recomputed

@@ -70,7 +70,28 @@ __device__ __forceinline__ void mma(f4v& c, const b8v& a, const b8v& b) {
 }
 
 __device__ __forceinline__ double act_tanh(double x) { return tanh(x); }
-__device__ __forceinline__ float act_tanh(float x) { return tanhf(x); }
+
+// Branch-free single-precision tanh, so that the epilogue's independent
+// values interleave.  |x| >= 0.4: the identity tanh|x| = 1 - 2 / (e^{2|x|} + 1)
+// with the hardware exponential (cancellation at most a factor 1.6 there);
+// |x| < 0.4: the Taylor series of tanh through x^13 (coefficients -1/3,
+// 2/15, -17/315, 62/2835, -1382/155925, 21844/6081075; the first omitted
+// term is below 2e-9 relative).  Odd symmetry restores the sign.
+__device__ __forceinline__ float act_tanh(float x) {
+    const float ax = fabsf(x);
+    const float e = __expf(2.0f * ax);
+    const float big = 1.0f - __fdividef(2.0f, e + 1.0f);
+    const float z = ax * ax;
+    float p = 21844.0f / 6081075.0f;
+    p = fmaf(p, z, -1382.0f / 155925.0f);
+    p = fmaf(p, z, 62.0f / 2835.0f);
+    p = fmaf(p, z, -17.0f / 315.0f);
+    p = fmaf(p, z, 2.0f / 15.0f);
+    p = fmaf(p, z, -1.0f / 3.0f);
+    const float small = fmaf(ax * z, p, ax);
+    const float r = ax < 0.4f ? small : (ax < 44.0f ? big : 1.0f);
+    return copysignf(r, x);
+}
 
 // ---------------------------------------------------------------------------
 // Workgroup -> (chain, tile).  Consecutive workgroup ids are dealt round-robin
@@ -87,17 +108,18 @@ __device__ __forceinline__ bool tile_of(int total, int per_chain, int& c, int& t
     return true;
 }
 
-// Deterministic workgroup sum: fixed butterfly within each wave, then the four
-// wave sums in wave order.  Every thread returns the same value.
+// Deterministic workgroup sum: fixed butterfly within each wave, then the
+// wave sums in wave order (blockDim.x / 64 waves, at most NWAVE).  Every
+// thread returns the same value.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
     double s = scratch[0];
-#pragma unroll
-    for (int w = 1; w < NWAVE; ++w) s += scratch[w];
+    for (int w = 1; w < nw; ++w) s += scratch[w];
     __syncthreads();
     return s;
 }
@@ -108,7 +130,7 @@ template <class T, int R>
 __device__ __forceinline__ void load_rows(T* dst, int ld, const T* src, int w) {
     constexpr int E = 16 / sizeof(T);
     const int cpr = w / E;
-    for (int i = threadIdx.x; i < R * cpr; i += HMC_NT) {
+    for (int i = threadIdx.x; i < R * cpr; i += blockDim.x) {
         const int r = i / cpr, q = i - r * cpr;
         *reinterpret_cast<uint4*>(dst + r * ld + q * E) =
             *reinterpret_cast<const uint4*>(src + (size_t)r * w + q * E);
@@ -130,52 +152,39 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
     constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
     constexpr int GK = 4 * KCH;              // K extent of one group of four chunks
     constexpr int RG = (R / 16) / NRB;
+    // With a single row block per unit the four chunks of a group feed four
+    // separate accumulators (summed at the end), so consecutive MFMAs do not
+    // wait on each other.
+    constexpr int KS = NRB == 1 ? 4 : 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (int)(blockDim.x >> 6);
     const int g = lane >> 4, li = lane & 15;
     // f64 16x16x4 returns accumulator rows g + 4v (f32 and bf16: 4g + v);
     // feeding A row 4 * (li % 4) + li / 4 from lane li makes the f64 outputs
     // land on rows 4g + v as well, so every epilogue sees the same layout.
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
     const int units = (Np >> 4) * RG;
-    const int my_units = units > wave ? (units - wave + NWAVE - 1) / NWAVE : 0;
+    const int my_units = units > wave ? (units - wave + nwave - 1) / nwave : 0;
     const int ng = K / GK;                   // full groups; K % GK chunks follow per unit
     const int rem = (K - ng * GK) / KCH;
+    const int steps = my_units * ng;
     // Weight fragments of the wave's whole (unit, group) stream are loaded one
-    // group ahead, so the L2 latency of group s+1 overlaps the MFMAs of group s.
+    // group ahead (two buffers, used alternately by an unrolled pair of
+    // steps), so the L2 latency of step s+1 overlaps the MFMAs of step s.
     auto wrow = [&](int ui) {
-        const int u = wave + ui * NWAVE;
+        const int u = wave + ui * nwave;
         return Wm + (size_t)((u / RG) * 16 + arow) * ldw + g * VEC;
     };
-    Frag aA[4], aB[4];
-    const int steps = my_units * ng;
     auto load_group = [&](Frag* a, int st) {
         const T* wr = wrow(st / ng) + (st % ng) * GK;
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
     };
-    if (steps > 0) load_group(aA, 0);
-    int st = 0;
-    for (int ui = 0; ui < my_units; ++ui) {
-        const int u = wave + ui * NWAVE;
+    Acc acc[NRB][KS];
+    auto finish_unit = [&](int ui) {
+        const int u = wave + ui * nwave;
         const int nb = u / RG, rg = u - nb * RG;
         const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
-        Acc acc[NRB];
-#pragma unroll
-        for (int i = 0; i < NRB; ++i) acc[i] = Acc{};
-        for (int grp = 0; grp < ng; ++grp, ++st) {
-            // ping-pong between the two fragment buffers without dynamic indexing
-            Frag* cur = (st & 1) ? aB : aA;
-            Frag* nxt = (st & 1) ? aA : aB;
-            if (st + 1 < steps) load_group(nxt, st + 1);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int i = 0; i < NRB; ++i) {
-                    const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + grp * GK + q * KCH);
-                    mma(acc[i], cur[q], b);
-                }
-            }
-        }
         if (rem) {
             const T* wr = wrow(ui) + ng * GK;
             for (int c = 0; c < rem; ++c) {
@@ -183,20 +192,73 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
 #pragma unroll
                 for (int i = 0; i < NRB; ++i) {
                     const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
-                    mma(acc[i], a, b);
+                    mma(acc[i][0], a, b);
                 }
             }
         }
 #pragma unroll
-        for (int i = 0; i < NRB; ++i) epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, acc[i]);
+        for (int i = 0; i < NRB; ++i) {
+            Acc t = acc[i][0];
+#pragma unroll
+            for (int q = 1; q < KS; ++q) t += acc[i][q];
+            epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, t);
+#pragma unroll
+            for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
+        }
+    };
+    auto step = [&](const Frag* a, int st) {
+        const int ui = st / ng, grp = st - ui * ng;
+        const int u = wave + ui * nwave;
+        const int rg = u % RG;
+        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC + grp * GK;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) {
+                const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + q * KCH);
+                mma(acc[i][q % KS], a[q], b);
+            }
+        }
+        if (grp == ng - 1) finish_unit(ui);
+    };
+#pragma unroll
+    for (int i = 0; i < NRB; ++i)
+#pragma unroll
+        for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
+    if (ng == 0) {
+        for (int ui = 0; ui < my_units; ++ui) finish_unit(ui);
+        return;
+    }
+    Frag aA[4], aB[4];
+    if (steps > 0) load_group(aA, 0);
+    for (int st = 0; st < steps; st += 2) {
+        if (st + 1 < steps) load_group(aB, st + 1);
+        step(aA, st);
+        if (st + 1 >= steps) break;
+        if (st + 2 < steps) load_group(aA, st + 2);
+        step(aB, st + 1);
     }
 }
 
+// Row blocks per unit: as many as keep every wave busy (more row blocks per
+// unit reuse each weight fragment more often).
 template <int P, int R, class Epi>
 __device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K, int Np,
                                      const typename PT<P>::T* X, int ldx, Epi& epi) {
-    if ((Np >> 4) >= NWAVE) gemm_units<P, R, R / 16>(Wm, ldw, K, Np, X, ldx, epi);
-    else gemm_units<P, R, 1>(Wm, ldw, K, Np, X, ldx, epi);
+    constexpr int RB = R / 16;
+    const int NB = Np >> 4;
+    const int nwave = (int)(blockDim.x >> 6);
+    if (NB >= nwave) {
+        gemm_units<P, R, RB>(Wm, ldw, K, Np, X, ldx, epi);
+        return;
+    }
+    if constexpr (RB >= 2) {
+        if (NB * 2 >= nwave) {
+            gemm_units<P, R, RB / 2>(Wm, ldw, K, Np, X, ldx, epi);
+            return;
+        }
+    }
+    gemm_units<P, R, 1>(Wm, ldw, K, Np, X, ldx, epi);
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +407,7 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
                                             const typename PT<P>::T* X, int lx,
                                             typename PT<P>::A* __restrict__ part) {
     typedef typename PT<P>::A A;
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += HMC_NT) {
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += (int)blockDim.x) {
         const int cd = code[k];
         const int i = cd >> 16, j = cd & 0xFFFF;
         A s = (A)0;
@@ -381,7 +443,8 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
     const int UI = (NI + BI - 1) / BI, UJ = (NJ + BJ - 1) / BJ;
     const int imax = NI * 16 - 1, jmax = NJ * 16 - 1;
-    for (int u = wave; u < UI * UJ; u += NWAVE) {
+    const int nwave = (int)(blockDim.x >> 6);
+    for (int u = wave; u < UI * UJ; u += nwave) {
         const int ui = u / UJ, uj = u - ui * UJ;
         Acc acc[BI][BJ];
         int ic[BI], jc[BJ];
@@ -431,13 +494,14 @@ __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, con
                                          int out_w, int in_w, int NI, int NJ, const int* pos,
                                          typename PT<P>::A* part) {
     if constexpr (R % PT<P>::KCH == 0) {
+        const int nwave = (int)(blockDim.x >> 6);
         if constexpr (P != 0) {
-            if ((NI / 4) * (NJ / 4) >= NWAVE) {
+            if ((NI / 4) * (NJ / 4) >= nwave) {
                 dw_dense_units<P, R, 4, 4>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
                 return;
             }
         }
-        if ((NI / 2) * (NJ / 2) >= NWAVE) dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
+        if ((NI / 2) * (NJ / 2) >= nwave) dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
         else dw_dense_units<P, R, 1, 1>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
     }
 }
@@ -512,6 +576,124 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     const double sq = block_sum(h.sq, red);
     if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
     if constexpr (!FWD) tower_backward<P, R>(a, tp, c, t, W, sm);
+}
+
+// Resident MLP kernel for networks whose weights fit in LDS beside the
+// activation slabs.  One workgroup per (chain, group of tpw row tiles):
+// the chain's weights are copied into LDS once (rows padded by 16 bytes, so
+// the 16 lanes of a fragment read hit distinct banks), then every tile runs
+// forward, FP64 head and adjoint from LDS.  Thread tid owns the selected
+// entries tid + 256 m (m < KPT) of its chain and sums their weight-gradient
+// terms over all its tiles in registers; one partial set per workgroup goes
+// to memory (the update kernel sums the groups in a fixed order).
+template <int P, int R, int KPT>
+__global__ __launch_bounds__(HMC_NT) void k_mlp_res(const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    double* red = reinterpret_cast<double*>(smem + a.red_off);
+    int c, grp;
+    if (!tile_of(a.n_chains * a.groups, a.groups, c, grp)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    T* smw = sm + a.w_lds_off;
+    // weights -> LDS, row by row into the padded layout
+    {
+        constexpr int E = 16 / sizeof(T);
+        for (int l = 0; l < tp.nl; ++l) {
+            const int in = tp.wp[l], out = tp.wp[l + 1];
+            const int cw = in / E, ct = out / E;
+            for (int i = threadIdx.x; i < out * cw; i += blockDim.x) {
+                const int r = i / cw, q = i - r * cw;
+                *reinterpret_cast<uint4*>(smw + tp.lwo[l] + r * (in + E) + q * E) =
+                    *reinterpret_cast<const uint4*>(W + tp.wo[l] + (size_t)r * in + q * E);
+            }
+            for (int i = threadIdx.x; i < in * ct; i += blockDim.x) {
+                const int r = i / ct, q = i - r * ct;
+                *reinterpret_cast<uint4*>(smw + tp.lwto[l] + r * (out + E) + q * E) =
+                    *reinterpret_cast<const uint4*>(W + tp.wto[l] + (size_t)r * out + q * E);
+            }
+        }
+    }
+    // the entries this thread owns: code and layer
+    const long long o = a.offs[c];
+    const int n = (int)(a.offs[c + 1] - o);
+    const int* seg = a.seg + (size_t)c * a.nseg;
+    int code[KPT], lay[KPT];
+    A acc[KPT];
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const int k = threadIdx.x + m * HMC_NT;
+        acc[m] = (A)0;
+        lay[m] = -1;
+        code[m] = 0;
+        if (k < n) {
+            code[m] = a.ecode[o + k];
+            int l = 0;
+            while (l + 1 < tp.nl && k >= seg[l + 1]) ++l;
+            lay[m] = l;
+        }
+    }
+    int lowest = tp.nl;
+    for (int l = 0; l < tp.nl; ++l)
+        if (seg[l + 1] > seg[l]) { lowest = l; break; }
+    const int L = tp.nl - 1;
+    constexpr int E = 16 / sizeof(T);
+    double sq = 0.0;
+    for (int tt = 0; tt < a.tpw; ++tt) {
+        const int t = grp * a.tpw + tt;
+        if (t >= a.tiles_a) break;
+        __syncthreads();
+        load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0],
+                        tp.wp[0]);
+        __syncthreads();
+        for (int l = 0; l < L; ++l) {
+            EpiTanh<P> e{B + tp.bo[l], sm + tp.lo[l + 1], tp.ls[l + 1]};
+            gemm<P, R>(smw + tp.lwo[l], tp.wp[l] + E, tp.wp[l], tp.wp[l + 1], sm + tp.lo[l], tp.ls[l], e);
+            __syncthreads();
+        }
+        EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target, a.d_out, t * R, a.n_rows_a,
+                        a.inv_lik_var, 0.0};
+        gemm<P, R>(smw + tp.lwo[L], tp.wp[L] + E, tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
+        sq += h.sq;
+        __syncthreads();
+        for (int l = L; l >= lowest; --l) {
+            const T* D = sm + tp.lo[l + 1];
+            const T* X = sm + tp.lo[l];
+            const int ld = tp.ls[l + 1], lx = tp.ls[l];
+#pragma unroll
+            for (int m = 0; m < KPT; ++m) {
+                if (lay[m] != l) continue;
+                const int i = code[m] >> 16, j = code[m] & 0xFFFF;
+                A s = (A)0;
+                if (j == 0xFFFF) {
+#pragma unroll 8
+                    for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
+                } else {
+#pragma unroll 8
+                    for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+                }
+                acc[m] += s;
+            }
+            if (l > lowest) {
+                __syncthreads();
+                EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};
+                gemm<P, R>(smw + tp.lwto[l], tp.wp[l + 1] + E, tp.wp[l + 1], tp.wp[l], sm + tp.lo[l + 1],
+                           tp.ls[l + 1], e);
+                __syncthreads();
+            }
+        }
+    }
+    A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)grp * n;
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const int k = threadIdx.x + m * HMC_NT;
+        if (k < n) part[k] = acc[m];
+    }
+    const double s = block_sum(sq, red);
+    if (threadIdx.x == 0) a.ulik[(size_t)c * a.groups + grp] = 0.5 * a.inv_lik_var * s;
 }
 
 // DeepONet trunk forward: T = trunk(y_q) for one (chain, query tile).
@@ -881,6 +1063,8 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if constexpr (P == 1) {
         if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_branch_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
@@ -914,45 +1098,61 @@ hipError_t hmc_set_lds_limit(int P, int R, size_t lds) {
 }
 
 #define HMC_TILE_CALL_k_mlp_grad(p, r) \
-    hipLaunchKernelGGL((k_mlp_grad<p, r, false>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_mlp_grad<p, r, false>), dim3(grid), dim3(nt), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_trunk_fwd(p, r) \
-    hipLaunchKernelGGL((k_trunk_fwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_trunk_fwd<p, r>), dim3(grid), dim3(nt), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_branch_grad(p, r) \
-    hipLaunchKernelGGL((k_branch_grad<p, r, false>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_branch_grad<p, r, false>), dim3(grid), dim3(nt), lds, s, a); return hipGetLastError()
 #define HMC_TILE_CALL_k_trunk_bwd(p, r) \
-    hipLaunchKernelGGL((k_trunk_bwd<p, r>), dim3(grid), dim3(HMC_NT), lds, s, a); return hipGetLastError()
+    hipLaunchKernelGGL((k_trunk_bwd<p, r>), dim3(grid), dim3(nt), lds, s, a); return hipGetLastError()
 
-hipError_t hmc_launch_mlp_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+// nt: threads per workgroup, 256 or 512 (the tile kernels are written for
+// any multiple of 64 up to HMC_NT).
+hipError_t hmc_launch_mlp_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_mlp_grad)
 }
-hipError_t hmc_launch_trunk_fwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t hmc_launch_trunk_fwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_trunk_fwd)
 }
-hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t hmc_launch_branch_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_branch_grad)
 }
-hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_trunk_bwd)
 }
 
 // FP32 energy pass (forward and likelihood partials only).
-hipError_t hmc_launch_mlp_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     switch (R) {
-        case 16: hipLaunchKernelGGL((k_mlp_grad<1, 16, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_mlp_grad<1, 32, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
-        case 64: hipLaunchKernelGGL((k_mlp_grad<1, 64, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_mlp_grad<1, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_mlp_grad<1, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_mlp_grad<1, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-hipError_t hmc_launch_branch_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     switch (R) {
-        case 16: hipLaunchKernelGGL((k_branch_grad<1, 16, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_branch_grad<1, 32, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
-        case 64: hipLaunchKernelGGL((k_branch_grad<1, 64, true>), dim3(grid), dim3(HMC_NT), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_branch_grad<1, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_branch_grad<1, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_branch_grad<1, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int P, int R, int KPT>
+hipError_t launch_res(const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_mlp_res<P, R, KPT>), dim3(grid), dim3(HMC_NT), lds, s, a);
+    return hipGetLastError();
+}
+
+// Resident MLP kernel; kpt = selected entries per thread (4 or 8).
+hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+#define C_(p, r)                                                                   \
+    return kpt <= 4 ? launch_res<p, r, 4>(a, grid, lds, s) : launch_res<p, r, 8>(a, grid, lds, s)
+    HMC_DISPATCH_PR(P, R, C_)
+#undef C_
 }
 
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st) {

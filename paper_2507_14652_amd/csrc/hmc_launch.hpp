@@ -6,12 +6,13 @@
 #include "hmc_plan.hpp"
 
 hipError_t hmc_set_lds_limit(int P, int R, size_t lds_bytes);
-hipError_t hmc_launch_mlp_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_trunk_fwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_branch_grad(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_trunk_bwd(int P, int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_mlp_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_branch_energy(int R, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_trunk_fwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_branch_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
 hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);

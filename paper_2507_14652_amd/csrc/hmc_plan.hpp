@@ -12,7 +12,7 @@
 #include <stdint.h>
 
 #define HMC_MAXL 8    // linear layers per tower
-#define HMC_NT 256    // threads per workgroup of the tile kernels (4 waves)
+#define HMC_NT 512    // threads per workgroup of the tile kernels (8 waves)
 
 struct TowerPlan {
     int nl;                     // linear layers
@@ -24,6 +24,8 @@ struct TowerPlan {
     long long wto[HMC_MAXL];    // offset of W_l^T
     long long bo[HMC_MAXL];     // offset of b_l in the per-chain bias buffer
     long long fo[HMC_MAXL];     // flat parameter index of W_l[0][0]
+    int lwo[HMC_MAXL];          // resident kernels: LDS offset (elements) of W_l, rows padded
+    int lwto[HMC_MAXL];         // resident kernels: LDS offset of W_l^T, rows padded
     int seg0;                   // first layer of this tower in the segment table
 };
 
@@ -69,6 +71,11 @@ struct GradArgs {
     int dg_off;                 // LDS offset (elements) of the [R][nq_pad + pad] output-adjoint slab
     int dg_ld;
     int red_off;                // LDS byte offset of the reduction scratch
+    // Resident MLP kernel: weights held in LDS, several row tiles per
+    // workgroup, selected-entry partials accumulated in registers.
+    int w_lds_off;              // LDS offset (elements) of the weight copy
+    int tpw;                    // row tiles per workgroup
+    int groups;                 // workgroups per chain (partials per chain)
 };
 
 // Arguments of the per-entry kernels (reduction of partials, kicks, drifts,

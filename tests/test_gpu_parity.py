@@ -199,3 +199,41 @@ def test_bf16_weight_gradient_paths_agree(name, kw, monkeypatch):
     e = _rel(out["dense"], out["gather"])
     print(f"bf16 {name}: dense vs gather {e:.2e}")
     assert 0 < e <= 1e-5   # nonzero: the two paths really differ in summation order
+
+
+@pytest.mark.parametrize("resident", ["1", "0"])
+@pytest.mark.parametrize("name,kw,prec", [
+    ("sine1d_fp64", dict(n_rows=256), "fp64"),
+    ("regress2d_fp32", dict(n_rows=1000, n_chains=3), "fp32"),
+    ("regress2d_fp32", dict(n_rows=4096, n_chains=8), "fp32"),
+    ("regress2d_fp32", dict(n_rows=1000, n_chains=3), "bf16"),
+])
+def test_resident_and_streaming_mlp_kernels(name, kw, prec, resident, monkeypatch):
+    """The MLP gradient from the resident kernel (weights in LDS, several row
+    tiles per workgroup, partials summed in registers) and from the streaming
+    kernel (one row tile per workgroup) both match the oracle; a trajectory
+    too."""
+    monkeypatch.setenv("HMC_RESIDENT", resident)
+    w = workloads.make(name, **kw)
+    s = _sampler(w, precision=prec)
+    U, g = s.grad()
+    g = g.double().cpu().numpy()
+    tol = {"fp64": 1e-11, "fp32": 1e-5, "bf16": BF16_GRAD_BOUND}[prec]
+    for c in range(w.n_chains):
+        post = on.posterior_for_chain(w, c)
+        Ur, gr = post.potential_and_grad(_state0(w, c, prec))
+        sl = slice(w.offs[c], w.offs[c + 1])
+        assert abs(U[c] - Ur) <= min(tol, 1e-5) * abs(Ur)
+        assert _rel(g[sl], gr) <= tol
+    if prec != "bf16":
+        dt = np.float64 if prec == "fp64" else np.float32
+        p0 = np.random.default_rng(2).standard_normal(w.nnz).astype(dt)
+        th, _, _, H1 = s.trajectory(p0, w.eps, 10)
+        th = th.double().cpu().numpy()
+        c = w.n_chains - 1
+        sl = slice(w.offs[c], w.offs[c + 1])
+        post = on.posterior_for_chain(w, c)
+        tr, pr, Ur, _ = oh.leapfrog(post.potential_and_grad, _state0(w, c, prec), p0[sl].astype(np.float64),
+                                    w.eps, 10)
+        assert np.abs(th[sl] - tr).max() <= REL[prec] * np.abs(tr).max()
+    s.close()
