@@ -8,7 +8,8 @@ gradient evaluations per second summed over chains.
 
 Prints one JSON line.  The default workload is the FP32 MLP regression
 (2-64-64-64-1 tanh, 4096 rows, 10% of the parameters sampled, 8 chains,
-L = 50, eps = 5e-4); --config selects another named workload.
+L = 50, per-chain step sizes adapted from 5e-4 to 80% acceptance before the
+timed region); --config selects another named workload.
 """
 
 from __future__ import annotations
@@ -267,6 +268,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-reps", type=int, default=50)
+    ap.add_argument("--adapt", type=int, default=150,
+                    help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
     args = ap.parse_args()
@@ -279,6 +282,7 @@ def main():
 
     import workloads
     from paper_2507_14652_amd import Sampler
+    from paper_2507_14652_amd.warmup import adapt_step_size
 
     w = workloads.make(args.config)
     s = Sampler.from_workload(w, seed=2507)
@@ -286,11 +290,14 @@ def main():
     st_dtype = torch.float64 if w.precision == "fp64" else torch.float32
     out = torch.empty((args.steps, w.nnz), dtype=st_dtype, device="cuda")
     warm = torch.empty((max(args.warmup, 1), w.nnz), dtype=st_dtype, device="cuda")
+    # untimed: per-chain step sizes by dual averaging to 80% acceptance, then
+    # the warm-up iterations at those step sizes
+    eps_c = adapt_step_size(s, w.eps, L, n_adapt=args.adapt) if args.adapt else np.full(C, w.eps)
     if args.warmup:
-        s.sample(args.warmup, w.eps, L, out=warm)
+        s.sample(args.warmup, eps_c, L, out=warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, stats = s.sample(args.steps, w.eps, L, out=out)
+    _, stats = s.sample(args.steps, eps_c, L, out=out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -321,7 +328,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "net": w.kind, "widths_a": w.widths_a, "widths_b": w.widths_b,
                    "rows": w.n_rows(), "chains": C, "selected_per_chain": int(w.nnz // C), "L": L,
-                   "eps": w.eps},
+                   "eps_start": w.eps, "eps_adapt_iters": args.adapt,
+                   "eps_median": float(np.median(eps_c)), "eps_min": float(np.min(eps_c)),
+                   "eps_max": float(np.max(eps_c))},
         "acceptance": acc,
         "kernel_ms": {"grad_main": ms[0], "trunk_fwd": ms[1], "trunk_bwd": ms[2], "reduce": ms[3]},
         "roofline": roof,

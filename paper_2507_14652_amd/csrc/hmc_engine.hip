@@ -248,32 +248,42 @@ void fill_plan_energy(TowerPlan& tp, const TowerPlan& src, int R) {
     for (int l = 0; l <= src.nl; ++l) tp.lo[l] = (l % 2) * R * mx;
 }
 
+// LDS bytes of a tower's staged biases: the padded widths of precision
+// prec, stored in the accumulator type (as bytes each).
+size_t bias_bytes(const std::vector<int>& w, int prec, size_t as) {
+    size_t n = 0;
+    for (size_t l = 1; l < w.size(); ++l) n += (size_t)roundup(w[l], pad_of(prec));
+    return (n * as + 15) / 16 * 16;
+}
+
 size_t energy_lds(const TowerPlan& src, int R) {
     int mx = 0;
     for (int l = 0; l <= src.nl; ++l) mx = std::max(mx, src.wp[l] + 4);
     return ((size_t)2 * R * mx * 4 + 15) / 16 * 16;
 }
 
-int pick_rows_energy(const TowerPlan& src) {
+// fixed: bytes beside the slabs (staged biases); per_row: bytes per tile row
+// (staged targets).
+int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
     for (int R : {64, 32, 16})
-        if (energy_lds(src, R) + 64 <= g_lds_cap) return R;
+        if (energy_lds(src, R) + 64 + fixed + per_row * R <= g_lds_cap) return R;
     return 0;
 }
 
 // Largest row tile whose LDS footprint fits, shrunk while the grid would
 // leave most compute units idle.  HMC_ROWS_A / HMC_ROWS_B override it.
-int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, long long rows, int chains,
+// fixed: bytes beside the slabs (staged biases, alignment).
+int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
               const char* env) {
+    auto fits = [&](int r) { return tower_lds(w, prec, r) + extra_per_row * r + 64 + 16 + fixed <= g_lds_cap; };
     if (const char* s = std::getenv(env)) {
         const int r = std::atoi(s);
-        if ((r == 16 || r == 32 || r == 64) && tower_lds(w, prec, r) + extra_per_row * r + 64 <= g_lds_cap) return r;
+        if ((r == 16 || r == 32 || r == 64) && fits(r)) return r;
     }
     int best = 0;
     for (int R : {64, 32, 16})
-        if (tower_lds(w, prec, R) + extra_per_row * R + 64 <= g_lds_cap) { best = R; break; }
-    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 512 &&
-           tower_lds(w, prec, best / 2) + extra_per_row * (best / 2) + 64 <= g_lds_cap)
-        best /= 2;
+        if (fits(R)) { best = R; break; }
+    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 512 && fits(best / 2)) best /= 2;
     return best;
 }
 
@@ -367,13 +377,15 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     int nq_pad = 0;
     if (x->kind == HMC_MLP) {
         rows_a = data->n_rows;
-        x->Ra = pick_rows(x->A.w, prec, 0, rows_a, x->C, "HMC_ROWS_A");
+        x->Ra = pick_rows(x->A.w, prec, (size_t)x->A.w.back() * 8, bias_bytes(x->A.w, prec, as), rows_a, x->C,
+                          "HMC_ROWS_A");
     } else {
         rows_a = data->n_u;
         rows_b = data->n_q;
         nq_pad = roundup((int)rows_b, pad);
-        x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, rows_a, x->C, "HMC_ROWS_A");
-        x->Rb = pick_rows(x->B.w, prec, 0, rows_b, x->C, "HMC_ROWS_B");
+        x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, bias_bytes(x->A.w, prec, as), rows_a,
+                          x->C, "HMC_ROWS_A");
+        x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B");
         if (!x->Rb) return x->fail(HMC_EUNSUPPORTED, "trunk tower does not fit in LDS");
     }
     if (!x->Ra) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS at 16 rows per tile");
@@ -497,12 +509,18 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     x->lds_a = (x->lds_a + 15) / 16 * 16;
     g.red_off = (int)x->lds_a;
     x->lds_a += 64;
+    g.bias_lds_a = (int)x->lds_a;
+    x->lds_a += bias_bytes(x->A.w, prec, as);
+    g.y_lds = (int)x->lds_a;
+    if (x->kind == HMC_MLP) x->lds_a += (size_t)x->Ra * x->A.w.back() * 8;
     // The per-kernel limit is set to the device capacity (not this engine's
     // size) so that engines of different shapes in one process coexist.
     HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
     x->nt_a = pick_threads(x->lds_a);
     if (x->kind == HMC_DEEPONET) {
         x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
+        g.bias_lds_b = (int)x->lds_b;
+        x->lds_b += bias_bytes(x->B.w, prec, as);
         HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
         x->nt_b = pick_threads(x->lds_b);
     }
@@ -590,18 +608,25 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     }
 
     // Per layer: where its bias entries start, and whether its weight partials
-    // come from a dense tile product (selected entries picked through a
-    // position map) or from per-entry sums.  The dense product does work in
-    // proportion to in*out and the per-entry sums in proportion to the
-    // selected count, but its stores are scattered through the position map;
-    // measured on MI355X it is slower at every density of the named
-    // workloads, so per-entry sums are the default and HMC_DW=dense selects
-    // the dense product (for layers at or above the density threshold).
+    // come from a dense tile product (MFMA over the tile rows, selected
+    // entries picked through the layer's selection bitmap) or from per-entry
+    // sums (two LDS reads and one FMA per row and entry).  The dense product
+    // costs in proportion to in*out, the sums in proportion to the selected
+    // count.  Measured on MI355X: in BF16 (MFMA 16x faster than FP32) the
+    // dense product halves the 256-wide MLP at 1-20% density; in FP32 and
+    // FP64 it is slower than the sums at 10% density on 64-wide layers, and
+    // on narrow layers (one 16-wide block) the padded product is slower in
+    // every precision.  So the dense product is used for BF16 layers at least
+    // 64 wide on both sides with density >= 1/128.  HMC_DW=dense or
+    // HMC_DW=gather forces one path for every layer that the dense product
+    // supports (tile rows a multiple of the MFMA K chunk).
     const int nlt = la + lb;
     std::vector<int> bseg((size_t)x->C * std::max(nlt, 1)), dflag((size_t)x->C * std::max(nlt, 1));
     const char* dwenv = std::getenv("HMC_DW");
+    const bool force_dense = dwenv && !std::strcmp(dwenv, "dense");
+    const bool force_gather = dwenv && !std::strcmp(dwenv, "gather");
     const int kch = prec == HMC_BF16 ? 32 : 16;
-    const int thr = prec == HMC_BF16 ? 128 : 32;   // dense when density >= 1/thr
+    const int thr = 128;   // BF16: dense when density >= 1/thr
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
         const int64_t* id = mask->idx + o;
@@ -613,15 +638,19 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             bseg[(size_t)c * nlt + L] = b;
             const long long nw = b - seg[(size_t)c * nseg + L];
             const int R = L < la ? x->Ra : x->Rb;
-            const bool dense = dwenv && !std::strcmp(dwenv, "dense") && nw > 0 && R % kch == 0 &&
+            const bool can = nw > 0 && R % kch == 0;
+            const bool autod = prec == HMC_BF16 && tp.w[l] >= 64 && tp.w[l + 1] >= 64 &&
                                nw * thr >= (long long)tp.w[l] * tp.w[l + 1];
+            const bool dense = can && !force_gather && (force_dense || autod);
             dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
         }
     }
-    // Position maps: chain-local entry index of every flat parameter (-1 if
-    // fixed); chains with the same mask share one map.
-    std::vector<long long> pos_off(x->C);
-    std::vector<int> pos_h;
+    // Selection bitmaps of the dense layers: for row i of W_l and columns
+    // 32w .. 32w + 31, the bits of the selected columns and the number of
+    // selected weights of the layer before that word.  Chains with the same
+    // mask share one bitmap per layer.
+    std::vector<long long> mw_off((size_t)x->C * std::max(nlt, 1), -1);
+    std::vector<int2> mw_h;
     std::vector<int> distinct;   // first chain of each distinct mask
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
@@ -630,27 +659,48 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             const long long od = x->offs[d], nd = x->offs[d + 1] - od;
             if (nd == n && std::equal(mask->idx + o, mask->idx + o + n, mask->idx + od)) { same = d; break; }
         }
-        if (same >= 0) { pos_off[c] = pos_off[same]; continue; }
-        distinct.push_back(c);
-        pos_off[c] = (long long)pos_h.size();
-        pos_h.resize(pos_h.size() + (size_t)x->P, -1);
-        int* m = pos_h.data() + pos_off[c];
-        for (long long k = 0; k < n; ++k) m[mask->idx[o + k]] = (int)k;
+        if (same < 0) distinct.push_back(c);
+        for (int L = 0; L < nlt; ++L) {
+            if (!dflag[(size_t)c * nlt + L]) continue;
+            if (same >= 0 && dflag[(size_t)same * nlt + L]) {
+                mw_off[(size_t)c * nlt + L] = mw_off[(size_t)same * nlt + L];
+                continue;
+            }
+            const TowerPlan& tp = *lplan[L];
+            const int l = lidx[L];
+            const int in = tp.w[l], out = tp.w[l + 1];
+            const int nwr = (in + 31) / 32;
+            const long long base = (long long)mw_h.size();
+            mw_off[(size_t)c * nlt + L] = base;
+            mw_h.resize(mw_h.size() + (size_t)out * nwr, int2{0, 0});
+            const int k0 = seg[(size_t)c * nseg + L], k1 = bseg[(size_t)c * nlt + L];
+            for (int k = k0; k < k1; ++k) {
+                const long long off = mask->idx[o + k] - lstart[L];
+                const int i = (int)(off / in), j = (int)(off % in);
+                mw_h[(size_t)(base + (long long)i * nwr + j / 32)].x |= (int)(1u << (j % 32));
+            }
+            int cnt = 0;
+            for (long long q = 0; q < (long long)out * nwr; ++q) {
+                int2& e = mw_h[(size_t)(base + q)];
+                e.y = cnt;
+                cnt += __builtin_popcount((unsigned)e.x);
+            }
+        }
     }
     int* bseg_d = (int*)x->dalloc(sizeof(int) * bseg.size());
     int* dflag_d = (int*)x->dalloc(sizeof(int) * dflag.size());
-    int* pos_d = (int*)x->dalloc(sizeof(int) * pos_h.size());
-    long long* posoff_d = (long long*)x->dalloc(sizeof(long long) * x->C);
-    if (!bseg_d || !dflag_d || !pos_d || !posoff_d) return x->fail(HMC_ENOMEM, "device allocation of the position maps failed");
+    int2* mw_d = (int2*)x->dalloc(sizeof(int2) * std::max<size_t>(mw_h.size(), 1));
+    long long* mwoff_d = (long long*)x->dalloc(sizeof(long long) * mw_off.size());
+    if (!bseg_d || !dflag_d || !mw_d || !mwoff_d) return x->fail(HMC_ENOMEM, "device allocation of the selection bitmaps failed");
     HMC_HIP(x, hipMemcpy(bseg_d, bseg.data(), sizeof(int) * bseg.size(), hipMemcpyHostToDevice));
     HMC_HIP(x, hipMemcpy(dflag_d, dflag.data(), sizeof(int) * dflag.size(), hipMemcpyHostToDevice));
-    HMC_HIP(x, hipMemcpy(pos_d, pos_h.data(), sizeof(int) * pos_h.size(), hipMemcpyHostToDevice));
-    HMC_HIP(x, hipMemcpy(posoff_d, pos_off.data(), sizeof(long long) * x->C, hipMemcpyHostToDevice));
+    if (!mw_h.empty()) HMC_HIP(x, hipMemcpy(mw_d, mw_h.data(), sizeof(int2) * mw_h.size(), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(mwoff_d, mw_off.data(), sizeof(long long) * mw_off.size(), hipMemcpyHostToDevice));
     g.bseg = bseg_d;
     g.dflag = dflag_d;
     g.nl_total = nlt;
-    g.pos = pos_d;
-    g.pos_off = posoff_d;
+    g.mw = mw_d;
+    g.mw_off = mwoff_d;
     x->dense_layers = (int)std::count(dflag.begin(), dflag.end(), 1);
 
     long long* offs_d = (long long*)x->dalloc(sizeof(long long) * (x->C + 1));
@@ -672,7 +722,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.nseg = nseg;
     g.tmax = x->resident ? x->groups : std::max(x->tiles_a, x->tiles_b);
     g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
-    g.ulik = (double*)x->dalloc(sizeof(double) * x->C * (x->resident ? x->groups : x->tiles_a));
+    g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * (x->resident ? x->groups : x->tiles_a));
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
 
     // BF16 engines: FP32 shadow for the energy pass (same offsets as wbuf).
@@ -683,7 +733,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->energy32 = true;
         GradArgs& e = x->ga32;
         e = g;
-        x->Ra32 = pick_rows_energy(g.ta);
+        x->Ra32 = pick_rows_energy(g.ta, bias_bytes(x->A.w, prec, 4), x->kind == HMC_MLP ? (size_t)x->A.w.back() * 8 : 0);
         if (!x->Ra32) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS for the FP32 energy pass");
         fill_plan_energy(e.ta, g.ta, x->Ra32);
         x->tiles_a32 = (int)((rows_a + x->Ra32 - 1) / x->Ra32);
@@ -691,6 +741,10 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->lds_a32 = energy_lds(g.ta, x->Ra32);
         e.red_off = (int)x->lds_a32;
         x->lds_a32 += 64;
+        e.bias_lds_a = (int)x->lds_a32;
+        x->lds_a32 += bias_bytes(x->A.w, prec, 4);
+        e.y_lds = (int)x->lds_a32;
+        if (x->kind == HMC_MLP) x->lds_a32 += (size_t)x->Ra32 * x->A.w.back() * 8;
         x->nt_a32 = pick_threads(x->lds_a32);
         std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
         fill_tower(w32h, HMC_FP32, g.ta, x->A);
@@ -709,17 +763,19 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             return d;
         };
         e.tiles_a = x->tiles_a32;
-        e.ulik = (double*)x->dalloc(sizeof(double) * x->C * x->tiles_a32);
+        e.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * x->tiles_a32);
         if (x->kind == HMC_MLP) {
             e.xa = upload32(data->x, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
         } else {
             e.xa = upload32(data->u, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
-            x->Rb32 = pick_rows_energy(g.tb);
+            x->Rb32 = pick_rows_energy(g.tb, bias_bytes(x->B.w, prec, 4), 0);
             if (!x->Rb32) return x->fail(HMC_EUNSUPPORTED, "trunk does not fit in LDS for the FP32 energy pass");
             fill_plan_energy(e.tb, g.tb, x->Rb32);
             x->tiles_b32 = (int)((rows_b + x->Rb32 - 1) / x->Rb32);
             x->grid_b32 = roundup(x->C * x->tiles_b32, 8);
             x->lds_b32 = energy_lds(g.tb, x->Rb32) + 64;
+            e.bias_lds_b = (int)x->lds_b32;
+            x->lds_b32 += bias_bytes(x->B.w, prec, 4);
             x->nt_b32 = pick_threads(x->lds_b32);
             e.tiles_b = x->tiles_b32;
             e.xb = upload32(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);

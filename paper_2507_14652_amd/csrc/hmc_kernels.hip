@@ -69,6 +69,20 @@ __device__ __forceinline__ void mma(f4v& c, const b8v& a, const b8v& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// One MFMA of a chunk: element e of the lane's K values (FP64 and FP32 take
+// four 16x16x4 MFMAs per 16-wide chunk, BF16 one 16x16x32).  NE<P> is the
+// number of MFMAs per chunk.
+template <int P> constexpr int NE = (P == 2) ? 1 : 4;
+__device__ __forceinline__ void mma1(d4v& c, const d4v& a, const d4v& b, int e) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma1(f4v& c, const f4v& a, const f4v& b, int e) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], c, 0, 0, 0);
+}
+__device__ __forceinline__ void mma1(f4v& c, const b8v& a, const b8v& b, int) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ double act_tanh(double x) { return tanh(x); }
 
 // Branch-free single-precision tanh, so that the epilogue's independent
@@ -138,6 +152,19 @@ __device__ __forceinline__ void load_rows(T* dst, int ld, const T* src, int w) {
 }
 
 // ---------------------------------------------------------------------------
+// Row blocks per unit: as many as keep every wave busy (more row blocks per
+// unit reuse each weight fragment more often).
+template <int R>
+__device__ __forceinline__ int nrb_of(int Np) {
+    constexpr int RB = R / 16;
+    const int NB = Np >> 4;
+    const int nwave = (int)(blockDim.x >> 6);
+    if (NB >= nwave) return RB;
+    if (RB >= 2 && NB * 2 >= nwave) return RB / 2;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
 // Tile product: for n in [0, Np) and r in [0, R)
 //     out^T[n][r] = sum_{k < K} Wm[n][k] * X[r][k]
 // Wm row stride ldw, X row stride ldx (LDS or global).  Work units are
@@ -189,11 +216,14 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
             const T* wr = wrow(ui) + ng * GK;
             for (int c = 0; c < rem; ++c) {
                 const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
+                Frag b[NRB];
 #pragma unroll
-                for (int i = 0; i < NRB; ++i) {
-                    const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
-                    mma(acc[i][0], a, b);
-                }
+                for (int i = 0; i < NRB; ++i)
+                    b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
+#pragma unroll
+                for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                    for (int i = 0; i < NRB; ++i) mma1(acc[i][0], a, b[i], e);
             }
         }
 #pragma unroll
@@ -206,18 +236,44 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
             for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
         }
     };
+    // One group (four chunks) of a unit.  MFMAs are issued element-major
+    // over independent accumulators (the NRB row blocks, or with one row
+    // block the four chunk accumulators), so consecutive MFMAs never wait on
+    // each other; the LDS fragments of chunk q + 1 are read while chunk q
+    // multiplies.
     auto step = [&](const Frag* a, int st) {
         const int ui = st / ng, grp = st - ui * ng;
         const int u = wave + ui * nwave;
         const int rg = u % RG;
         const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC + grp * GK;
+        if constexpr (NRB == 1) {
+            Frag b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 4; ++q) b[q] = *reinterpret_cast<const Frag*>(xr + q * KCH);
 #pragma unroll
-            for (int i = 0; i < NRB; ++i) {
-                const Frag b = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + q * KCH);
-                mma(acc[i][q % KS], a[q], b);
-            }
+            for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mma1(acc[0][q], a[q], b[q], e);
+        } else {
+            Frag bA[NRB], bB[NRB];
+            auto loadB = [&](Frag (&b)[NRB], int q) {
+#pragma unroll
+                for (int i = 0; i < NRB; ++i) b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + q * KCH);
+            };
+            auto mul = [&](const Frag (&b)[NRB], const Frag& aq) {
+#pragma unroll
+                for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                    for (int i = 0; i < NRB; ++i) mma1(acc[i][0], aq, b[i], e);
+            };
+            loadB(bA, 0);
+            loadB(bB, 1);
+            mul(bA, a[0]);
+            loadB(bA, 2);
+            mul(bB, a[1]);
+            loadB(bB, 3);
+            mul(bA, a[2]);
+            mul(bB, a[3]);
         }
         if (grp == ng - 1) finish_unit(ui);
     };
@@ -240,20 +296,17 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
     }
 }
 
-// Row blocks per unit: as many as keep every wave busy (more row blocks per
-// unit reuse each weight fragment more often).
 template <int P, int R, class Epi>
 __device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K, int Np,
                                      const typename PT<P>::T* X, int ldx, Epi& epi) {
     constexpr int RB = R / 16;
-    const int NB = Np >> 4;
-    const int nwave = (int)(blockDim.x >> 6);
-    if (NB >= nwave) {
+    const int nrb = nrb_of<R>(Np);
+    if (nrb == RB) {
         gemm_units<P, R, RB>(Wm, ldw, K, Np, X, ldx, epi);
         return;
     }
     if constexpr (RB >= 2) {
-        if (NB * 2 >= nwave) {
+        if (nrb == RB / 2) {
             gemm_units<P, R, RB / 2>(Wm, ldw, K, Np, X, ldx, epi);
             return;
         }
@@ -308,7 +361,8 @@ template <int P> struct EpiBack {
 
 // MLP output layer and squared-error head: F = z + b; residual in FP64;
 // delta = (F - y) / lik_sd^2 replaces the output; the squared residuals of
-// the valid rows accumulate per thread.
+// the valid rows accumulate per thread.  y points at the target of the
+// tile's row 0 (row r of the tile at y[r * d_out]).
 template <int P> struct EpiMlpHead {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const A* bias; T* out; int ld;
@@ -322,7 +376,7 @@ template <int P> struct EpiMlpHead {
             const int n = n0 + v;
             T d = (T)0;
             if (n < d_out && row < nrows) {
-                const double res = ((double)acc[v] + (double)bias[n]) - y[(size_t)row * d_out + n];
+                const double res = ((double)acc[v] + (double)bias[n]) - y[r * d_out + n];
                 sq += res * res;
                 d = (T)(A)(res * iv);
             }
@@ -400,44 +454,77 @@ template <int P> struct EpiCombine {
 // Masked weight gradient, one tile: for each selected entry k of the layer,
 //   part[k] = sum_r delta[r][i_k] * a[r][j_k]     (weights)
 //   part[k] = sum_r delta[r][i_k]                  (biases)
-// Rows past the data hold delta = 0 and contribute nothing.
+// Rows past the data hold delta = 0 and contribute nothing.  A layer with
+// few entries gives each entry LPE adjacent lanes (rows r = sub mod LPE,
+// then a fixed butterfly over the LPE lanes), so that short segments do not
+// leave most of the workgroup idle behind one R-long chain per entry.
 template <int P, int R>
 __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0, int k1,
                                             const typename PT<P>::T* D, int ld,
                                             const typename PT<P>::T* X, int lx,
                                             typename PT<P>::A* __restrict__ part) {
     typedef typename PT<P>::A A;
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += (int)blockDim.x) {
-        const int cd = code[k];
-        const int i = cd >> 16, j = cd & 0xFFFF;
-        A s = (A)0;
-        if (j == 0xFFFF) {
+    const int n = k1 - k0;
+    if (n <= 0) return;
+    const int nthr = (int)blockDim.x;
+    int lpe = 1;
+    while (lpe < 16 && 2 * lpe <= R && n * 2 * lpe <= nthr) lpe *= 2;
+    if (lpe == 1) {
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += nthr) {
+            const int cd = code[k];
+            const int i = cd >> 16, j = cd & 0xFFFF;
+            A s = (A)0;
+            if (j == 0xFFFF) {
 #pragma unroll 8
-            for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
-        } else {
+                for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
+            } else {
 #pragma unroll 8
-            for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+                for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+            }
+            part[k] = s;
         }
-        part[k] = s;
+        return;
     }
+    // n * lpe <= nthr: one pass; every lane of a wave takes part in the
+    // shuffles (lanes past the last entry sum nothing)
+    const int e = (int)threadIdx.x / lpe, sub = (int)threadIdx.x - e * lpe;
+    A s = (A)0;
+    if (e < n) {
+        const int cd = code[k0 + e];
+        const int i = cd >> 16, j = cd & 0xFFFF;
+        if (j == 0xFFFF) {
+            for (int r = sub; r < R; r += lpe) s += (A)D[r * ld + i];
+        } else {
+            for (int r = sub; r < R; r += lpe) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+        }
+    }
+    for (int o = 1; o < lpe; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (e < n && sub == 0) part[k0 + e] = s;
 }
 
 // Dense weight-gradient tile, selected entries kept: for output rows i and
 // input columns j of a layer,
 //   dW[i][j] = sum_r delta[r][i] * a[r][j]
-// as an MFMA product whose K dimension runs over the tile rows; each entry
-// with a position in the chain's map goes to part[pos].  The operands sit
-// row-major in LDS, so each lane reads its K values (consecutive rows) one
-// scalar at a time; BI x BJ register blocking reuses every fragment across
-// BJ (or BI) products.  Requires R to be a multiple of the K chunk.
+// as an MFMA product whose K dimension runs over the tile rows.  Which
+// entries are selected, and where each goes, comes from the layer's
+// selection bitmap: for row i and columns 32w .. 32w + 31 one word of bits
+// and the number of selected weights of the layer before that word, so the
+// chain-local index of entry (i, j) is kbase + prefix + popcount(bits below
+// j).  A lane's bitmap words depend only on its rows, so they are loaded
+// before the products and their latency hides behind the MFMAs.  The
+// operands sit row-major in LDS, so each lane reads its K values (one per
+// tile row) one scalar at a time; BI x BJ blocks per wave reuse them.
+// BJ is 1 or 2: the two column blocks of a unit share one bitmap word.
 template <int P, int R, int BI, int BJ>
 __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
                                                int lx, int out_w, int in_w, int NI, int NJ,
-                                               const int* __restrict__ pos, typename PT<P>::A* __restrict__ part) {
+                                               const int2* __restrict__ mw, int nwr, int kbase,
+                                               typename PT<P>::A* __restrict__ part) {
     typedef typename PT<P>::A A;
     typedef typename PT<P>::Acc Acc;
     typedef typename PT<P>::Frag Frag;
     constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
+    static_assert(BJ == 1 || BJ == 2, "one bitmap word per unit row");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
@@ -446,6 +533,15 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     const int nwave = (int)(blockDim.x >> 6);
     for (int u = wave; u < UI * UJ; u += nwave) {
         const int ui = u / UJ, uj = u - ui * UJ;
+        const int w = (uj * BJ * 16) >> 5;          // bitmap word of the unit's columns
+        int2 tw[BI][4];
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = (ui * BI + bi) * 16 + 4 * g + v;
+                tw[bi][v] = (i < out_w && w < nwr) ? mw[(size_t)i * nwr + w] : make_int2(0, 0);
+            }
         Acc acc[BI][BJ];
         int ic[BI], jc[BJ];
 #pragma unroll
@@ -468,21 +564,24 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
                 for (int bj = 0; bj < BJ; ++bj) b[bj][e] = X[(r0 + e) * lx + jc[bj]];
             }
 #pragma unroll
-            for (int bi = 0; bi < BI; ++bi)
+            for (int e = 0; e < NE<P>; ++e)
 #pragma unroll
-                for (int bj = 0; bj < BJ; ++bj) mma(acc[bi][bj], a[bi], b[bj]);
+                for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < BJ; ++bj) mma1(acc[bi][bj], a[bi], b[bj], e);
         }
 #pragma unroll
         for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
             for (int bj = 0; bj < BJ; ++bj) {
                 const int j = (uj * BJ + bj) * 16 + li;
+                const unsigned bit = (unsigned)j & 31u;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int i = (ui * BI + bi) * 16 + 4 * g + v;
-                    if (i < out_w && j < in_w) {
-                        const int k = pos[(size_t)i * in_w + j];
-                        if (k >= 0) part[k] = (A)acc[bi][bj][v];
+                    const unsigned bits = (unsigned)tw[bi][v].x;
+                    if (j < in_w && ((bits >> bit) & 1u)) {
+                        const int k = kbase + tw[bi][v].y + __popc(bits & ((1u << bit) - 1u));
+                        part[k] = (A)acc[bi][bj][v];
                     }
                 }
             }
@@ -491,21 +590,34 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 
 template <int P, int R>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
-                                         int out_w, int in_w, int NI, int NJ, const int* pos,
+                                         int out_w, int in_w, int NI, int NJ, const int2* mw, int kbase,
                                          typename PT<P>::A* part) {
     if constexpr (R % PT<P>::KCH == 0) {
         const int nwave = (int)(blockDim.x >> 6);
-        if constexpr (P != 0) {
-            if ((NI / 4) * (NJ / 4) >= nwave) {
-                dw_dense_units<P, R, 4, 4>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
-                return;
+        const int nwr = (in_w + 31) >> 5;
+        if (NJ >= 2) {
+            if constexpr (P != 0) {
+                if ((NI / 4) * (NJ / 2) >= nwave) {
+                    dw_dense_units<P, R, 4, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+                    return;
+                }
             }
+            dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+        } else {
+            dw_dense_units<P, R, 2, 1>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
         }
-        if ((NI / 2) * (NJ / 2) >= nwave) dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
-        else dw_dense_units<P, R, 1, 1>(D, ld, X, lx, out_w, in_w, NI, NJ, pos, part);
     }
 }
 
+// Lowest layer of the tower with selected entries in chain c (nl: none).
+__device__ __forceinline__ int lowest_layer(const GradArgs& a, const TowerPlan& tp, int c) {
+    const int* seg = a.seg + (size_t)c * a.nseg + tp.seg0;
+    for (int l = 0; l < tp.nl; ++l)
+        if (seg[l + 1] > seg[l]) return l;
+    return tp.nl;
+}
+
+// Hidden layers; B points at the tower's biases (staged in LDS).
 template <int P, int R>
 __device__ __forceinline__ void tower_hidden_forward(const TowerPlan& tp, const typename PT<P>::T* W,
                                                      const typename PT<P>::A* B, typename PT<P>::T* sm) {
@@ -516,27 +628,40 @@ __device__ __forceinline__ void tower_hidden_forward(const TowerPlan& tp, const 
     }
 }
 
+// Copies n values into LDS (biases, targets); the caller synchronises.
+template <class V>
+__device__ __forceinline__ void stage(V* dst, const V* src, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Likelihood partial of one tile, one slot per wave (the wave's lanes summed
+// by a fixed butterfly); slots of absent waves stay zero.
+__device__ __forceinline__ void ulik_store(double* slot8, double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) slot8[threadIdx.x >> 6] = v;
+}
+
 // Adjoint pass of one tower from the output adjoint held in slab nl: for each
 // layer from the top, the selected weight-gradient partials, then (while a
 // lower layer still has selected entries) the adjoint of the layer input.
+// lowest: lowest_layer() of the chain.
 template <int P, int R>
 __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, int c, int t,
-                                               const typename PT<P>::T* W, typename PT<P>::T* sm) {
+                                               const typename PT<P>::T* W, typename PT<P>::T* sm, int lowest) {
     typedef typename PT<P>::A A;
     const long long o = a.offs[c];
     const int n = (int)(a.offs[c + 1] - o);
     const int* code = a.ecode + o;
     const int* seg = a.seg + (size_t)c * a.nseg + tp.seg0;
     A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)t * n;
-    int lowest = tp.nl;
-    for (int l = 0; l < tp.nl; ++l)
-        if (seg[l + 1] > seg[l]) { lowest = l; break; }
     const int* bseg = a.bseg + (size_t)c * a.nl_total + tp.seg0;
     const int* dflag = a.dflag + (size_t)c * a.nl_total + tp.seg0;
     for (int l = tp.nl - 1; l >= lowest; --l) {
         if (dflag[l]) {
             dw_dense<P, R>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
-                           tp.wp[l + 1] >> 4, tp.wp[l] >> 4, a.pos + a.pos_off[c] + tp.fo[l], part);
+                           tp.wp[l + 1] >> 4, tp.wp[l] >> 4,
+                           a.mw + a.mw_off[(size_t)c * a.nl_total + tp.seg0 + l], seg[l], part);
             dw_partials<P, R>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
         } else {
             dw_partials<P, R>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
@@ -559,23 +684,35 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
-    double* red = reinterpret_cast<double*>(smem + a.red_off);
     int c, t;
     if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
     if (!a.active[c]) return;
     const TowerPlan& tp = a.ta;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    // biases and the tile's targets into LDS, beside the input rows
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    double* ys = reinterpret_cast<double*>(smem + a.y_lds);
+    {
+        const int nv = max(0, min(R, a.n_rows_a - t * R)) * a.d_out;
+        const double* yg = a.target + (size_t)t * R * a.d_out;
+        for (int i = threadIdx.x; i < R * a.d_out; i += blockDim.x) ys[i] = i < nv ? yg[i] : 0.0;
+    }
+    const A* B = Bs - tp.bo[0];
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
+    const int lowest = FWD ? tp.nl : lowest_layer(a, tp, c);
     tower_hidden_forward<P, R>(tp, W, B, sm);
-    const int L = tp.nl - 1;
-    EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target, a.d_out, t * R, a.n_rows_a,
+    EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], ys, a.d_out, t * R, a.n_rows_a,
                     a.inv_lik_var, 0.0};
     gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
-    const double sq = block_sum(h.sq, red);
-    if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
-    if constexpr (!FWD) tower_backward<P, R>(a, tp, c, t, W, sm);
+    ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * h.sq);
+    if constexpr (!FWD) {
+        __syncthreads();
+        tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
+    }
 }
 
 // Resident MLP kernel for networks whose weights fit in LDS beside the
@@ -654,7 +791,8 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_res(const GradArgs a) {
             gemm<P, R>(smw + tp.lwo[l], tp.wp[l] + E, tp.wp[l], tp.wp[l + 1], sm + tp.lo[l], tp.ls[l], e);
             __syncthreads();
         }
-        EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target, a.d_out, t * R, a.n_rows_a,
+        EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target + (size_t)t * R * a.d_out,
+                        a.d_out, t * R, a.n_rows_a,
                         a.inv_lik_var, 0.0};
         gemm<P, R>(smw + tp.lwo[L], tp.wp[L] + E, tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
         sq += h.sq;
@@ -693,7 +831,7 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_res(const GradArgs a) {
         if (k < n) part[k] = acc[m];
     }
     const double s = block_sum(sq, red);
-    if (threadIdx.x == 0) a.ulik[(size_t)c * a.groups + grp] = 0.5 * a.inv_lik_var * s;
+    if (threadIdx.x == 0) a.ulik[((size_t)c * a.groups + grp) * 8] = 0.5 * a.inv_lik_var * s;
 }
 
 // DeepONet trunk forward: T = trunk(y_q) for one (chain, query tile).
@@ -707,11 +845,14 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_fwd(const GradArgs a) {
     if (!a.active[c]) return;
     const TowerPlan& tp = a.tb;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_b);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xb) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
     tower_hidden_forward<P, R>(tp, W, B, sm);
-    const int L = tp.nl - 1;
     const int nvalid = a.n_rows_b - t * R;
     EpiTrunkOut<P> e{B + tp.bo[L], reinterpret_cast<T*>(a.tm) + c * a.tm_stride, tp.wp[L + 1],
                      reinterpret_cast<T*>(a.tt) + c * a.tm_stride, a.nq_rows, t * R, nvalid};
@@ -731,29 +872,35 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     if (!a.active[c]) return;
     const TowerPlan& tp = a.ta;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
-    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
-    __syncthreads();
-    tower_hidden_forward<P, R>(tp, W, B, sm);
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
     const int L = tp.nl - 1;
     const int pp = tp.wp[L + 1];
+    const double b0 = (double)Bg[a.b0_off];
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    const int lowest = FWD ? tp.nl : lowest_layer(a, tp, c);
+    tower_hidden_forward<P, R>(tp, W, B, sm);
     const int nvalid = a.n_rows_a - t * R;
+    const T* tmc = reinterpret_cast<const T*>(a.tm) + c * a.tm_stride;
+    const T* ttc = reinterpret_cast<const T*>(a.tt) + c * a.tm_stride;
     EpiBranchOut<P> eo{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1],
                        reinterpret_cast<T*>(a.btr) + c * a.bt_stride, a.nu_cols, t * R, nvalid, !FWD};
     gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], pp, sm + tp.lo[L], tp.ls[L], eo);
     __syncthreads();
     EpiCombine<P> ec{sm + a.dg_off, a.dg_ld, reinterpret_cast<T*>(a.dgt) + c * a.dgt_stride, a.nu_cols, t * R,
-                     a.target, a.nq, nvalid, t * R, (double)B[a.b0_off], a.inv_lik_var, !FWD, 0.0, 0.0};
-    gemm<P, R>(reinterpret_cast<const T*>(a.tm) + c * a.tm_stride, pp, pp, a.nq_pad, sm + tp.lo[L + 1],
-               tp.ls[L + 1], ec);
+                     a.target, a.nq, nvalid, t * R, b0, a.inv_lik_var, !FWD, 0.0, 0.0};
+    gemm<P, R>(tmc, pp, pp, a.nq_pad, sm + tp.lo[L + 1], tp.ls[L + 1], ec);
     const double sq = block_sum(ec.sq, red);
     if constexpr (FWD) {
-        if (threadIdx.x == 0) a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
+        if (threadIdx.x == 0) a.ulik[((size_t)c * a.tiles_a + t) * 8] = 0.5 * a.inv_lik_var * sq;
         return;
     }
     const double sdg = block_sum(ec.sdg, red);
     if (threadIdx.x == 0) {
-        a.ulik[(size_t)c * a.tiles_a + t] = 0.5 * a.inv_lik_var * sq;
+        a.ulik[((size_t)c * a.tiles_a + t) * 8] = 0.5 * a.inv_lik_var * sq;
         const long long o = a.offs[c];
         const int n = (int)(a.offs[c + 1] - o);
         const int* seg = a.seg + (size_t)c * a.nseg;
@@ -763,10 +910,9 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     }
     // adjoint of the branch output: dB = dG T, into the slab that held B
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
-    gemm<P, R>(reinterpret_cast<const T*>(a.tt) + c * a.tm_stride, a.nq_rows, a.nq_pad, pp, sm + a.dg_off,
-               a.dg_ld, es);
+    gemm<P, R>(ttc, a.nq_rows, a.nq_pad, pp, sm + a.dg_off, a.dg_ld, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, c, t, W, sm);
+    tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
 }
 
 // DeepONet trunk adjoint tile: recompute the trunk forward for the tile's
@@ -782,16 +928,21 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
     if (!a.active[c]) return;
     const TowerPlan& tp = a.tb;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_b);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xb) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
+    const int lowest = lowest_layer(a, tp, c);
+    const T* btc = reinterpret_cast<const T*>(a.btr) + c * a.bt_stride;
     tower_hidden_forward<P, R>(tp, W, B, sm);
-    const int L = tp.nl - 1;
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
-    gemm<P, R>(reinterpret_cast<const T*>(a.btr) + c * a.bt_stride, a.nu_cols, a.nu_cols, tp.wp[L + 1],
+    gemm<P, R>(btc, a.nu_cols, a.nu_cols, tp.wp[L + 1],
                reinterpret_cast<const T*>(a.dgt) + c * a.dgt_stride + (size_t)t * R * a.nu_cols, a.nu_cols, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, c, t, W, sm);
+    tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
 }
 
 // ---------------------------------------------------------------------------
@@ -970,7 +1121,9 @@ __global__ __launch_bounds__(256) void k_traj_end(const StateArgs s, int mode) {
     pri = 0.5 * s.inv_prior_var * block_sum(pri, red);
     kin = 0.5 * block_sum(kin, red);
     double ul = 0.0;
-    for (int t = 0; t < s.ulik_tiles; ++t) ul += s.ulik[(size_t)c * s.ulik_tiles + t];
+    const int nsl = s.ulik_tiles * 8;   // eight per-wave slots per tile
+    for (int t = threadIdx.x; t < nsl; t += 256) ul += s.ulik[(size_t)c * nsl + t];
+    ul = block_sum(ul, red);
     const double U1 = ul + pri;
     if (mode == END_ENERGY) {
         if (threadIdx.x == 0) s.U[c] = U1;

@@ -10,6 +10,7 @@
 //    longer needs.
 #pragma once
 #include <stdint.h>
+#include <hip/hip_runtime.h>
 
 #define HMC_MAXL 8    // linear layers per tower
 #define HMC_NT 512    // threads per workgroup of the tile kernels (8 waves)
@@ -54,11 +55,12 @@ struct GradArgs {
     const int* bseg;            // [C][nl_total] chain-local start of each layer's bias entries
     const int* dflag;           // [C][nl_total] 1: weight partials by a dense tile product
     int nl_total;
-    const int* pos;             // chain-local entry index of each flat parameter, -1 if fixed
-    const long long* pos_off;   // [C] offset of each chain's map in pos (equal masks share one)
+    const int2* mw;             // selection bitmaps of the dense layers: per row i and word w of
+                                //   32 columns, {bits, selected weights of the layer before it}
+    const long long* mw_off;    // [C][nl_total] offset of a (chain, layer) bitmap in mw (-1: none)
     void* part;                 // per-tile gradient partials, A
     long long tmax;             // tiles per chain in the partial layout
-    double* ulik;               // [C][tiles_a] likelihood partials
+    double* ulik;               // [C][tiles_a][8] likelihood partials (one slot per wave)
     double inv_lik_var;
     // DeepONet exchange buffers, T
     void* tm;                   // [C][nq_rows][p_p]   trunk features
@@ -71,6 +73,8 @@ struct GradArgs {
     int dg_off;                 // LDS offset (elements) of the [R][nq_pad + pad] output-adjoint slab
     int dg_ld;
     int red_off;                // LDS byte offset of the reduction scratch
+    int bias_lds_a, bias_lds_b; // LDS byte offsets of the staged biases of towers A and B
+    int y_lds;                  // LDS byte offset of the staged MLP targets of a tile [R][d_out]
     // Resident MLP kernel: weights held in LDS, several row tiles per
     // workgroup, selected-entry partials accumulated in registers.
     int w_lds_off;              // LDS offset (elements) of the weight copy
@@ -90,7 +94,7 @@ struct StateArgs {
     int tiles_a, tiles_b;
     long long tmax;
     const void* part;
-    const double* ulik;         // likelihood partials that define U (energy pass)
+    const double* ulik;         // likelihood partials that define U, [C][ulik_tiles][8]
     int ulik_tiles;
     void* theta;                // S [nnz]
     void* mom;                  // S [nnz]
