@@ -152,16 +152,15 @@ __device__ __forceinline__ void load_rows(T* dst, int ld, const T* src, int w) {
 }
 
 // ---------------------------------------------------------------------------
-// Row blocks per unit: as many as keep every wave busy (more row blocks per
-// unit reuse each weight fragment more often).
+// Row blocks per unit: all R / 16 of them (each weight fragment reused over
+// the whole tile) when the column blocks keep at least half the waves busy,
+// else one (narrow outputs: every wave takes a row block).  Two variants
+// only, to keep the kernels' code within the instruction cache.
 template <int R>
 __device__ __forceinline__ int nrb_of(int Np) {
-    constexpr int RB = R / 16;
     const int NB = Np >> 4;
     const int nwave = (int)(blockDim.x >> 6);
-    if (NB >= nwave) return RB;
-    if (RB >= 2 && NB * 2 >= nwave) return RB / 2;
-    return 1;
+    return NB * 2 >= nwave ? R / 16 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -169,7 +168,10 @@ __device__ __forceinline__ int nrb_of(int Np) {
 //     out^T[n][r] = sum_{k < K} Wm[n][k] * X[r][k]
 // Wm row stride ldw, X row stride ldx (LDS or global).  Work units are
 // (16-column block of n, NRB 16-row blocks of r); the A fragment (weights)
-// is loaded once per K chunk and reused over the NRB row blocks.
+// is loaded once per K chunk and reused over the NRB row blocks.  A wave
+// walks its (unit, group) steps in one loop: the weight fragments of step
+// s + 1 are loaded while step s multiplies (two fragment sets swapped each
+// step, so the loop body, and the epilogue, appear once in the code).
 template <int P, int R, int NRB, class Epi>
 __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__ Wm, int ldw, int K, int Np,
                                            const typename PT<P>::T* X, int ldx, Epi& epi) {
@@ -194,105 +196,98 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
     const int my_units = units > wave ? (units - wave + nwave - 1) / nwave : 0;
     const int ng = K / GK;                   // full groups; K % GK chunks follow per unit
     const int rem = (K - ng * GK) / KCH;
-    const int steps = my_units * ng;
-    // Weight fragments of the wave's whole (unit, group) stream are loaded one
-    // group ahead (two buffers, used alternately by an unrolled pair of
-    // steps), so the L2 latency of step s+1 overlaps the MFMAs of step s.
+    const int gpu = ng > 0 ? ng : 1;         // loop steps per unit (a unit with no full group still ends once)
+    const int steps = my_units * gpu;
     auto wrow = [&](int ui) {
         const int u = wave + ui * nwave;
         return Wm + (size_t)((u / RG) * 16 + arow) * ldw + g * VEC;
     };
-    auto load_group = [&](Frag* a, int st) {
-        const T* wr = wrow(st / ng) + (st % ng) * GK;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
-    };
     Acc acc[NRB][KS];
-    auto finish_unit = [&](int ui) {
-        const int u = wave + ui * nwave;
-        const int nb = u / RG, rg = u - nb * RG;
-        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
-        if (rem) {
-            const T* wr = wrow(ui) + ng * GK;
-            for (int c = 0; c < rem; ++c) {
-                const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
-                Frag b[NRB];
-#pragma unroll
-                for (int i = 0; i < NRB; ++i)
-                    b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
-#pragma unroll
-                for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                    for (int i = 0; i < NRB; ++i) mma1(acc[i][0], a, b[i], e);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < NRB; ++i) {
-            Acc t = acc[i][0];
-#pragma unroll
-            for (int q = 1; q < KS; ++q) t += acc[i][q];
-            epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, t);
-#pragma unroll
-            for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
-        }
-    };
-    // One group (four chunks) of a unit.  MFMAs are issued element-major
-    // over independent accumulators (the NRB row blocks, or with one row
-    // block the four chunk accumulators), so consecutive MFMAs never wait on
-    // each other; the LDS fragments of chunk q + 1 are read while chunk q
-    // multiplies.
-    auto step = [&](const Frag* a, int st) {
-        const int ui = st / ng, grp = st - ui * ng;
-        const int u = wave + ui * nwave;
-        const int rg = u % RG;
-        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC + grp * GK;
-        if constexpr (NRB == 1) {
-            Frag b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) b[q] = *reinterpret_cast<const Frag*>(xr + q * KCH);
-#pragma unroll
-            for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) mma1(acc[0][q], a[q], b[q], e);
-        } else {
-            Frag bA[NRB], bB[NRB];
-            auto loadB = [&](Frag (&b)[NRB], int q) {
-#pragma unroll
-                for (int i = 0; i < NRB; ++i) b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + q * KCH);
-            };
-            auto mul = [&](const Frag (&b)[NRB], const Frag& aq) {
-#pragma unroll
-                for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                    for (int i = 0; i < NRB; ++i) mma1(acc[i][0], aq, b[i], e);
-            };
-            loadB(bA, 0);
-            loadB(bB, 1);
-            mul(bA, a[0]);
-            loadB(bA, 2);
-            mul(bB, a[1]);
-            loadB(bB, 3);
-            mul(bA, a[2]);
-            mul(bB, a[3]);
-        }
-        if (grp == ng - 1) finish_unit(ui);
-    };
 #pragma unroll
     for (int i = 0; i < NRB; ++i)
 #pragma unroll
         for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
-    if (ng == 0) {
-        for (int ui = 0; ui < my_units; ++ui) finish_unit(ui);
-        return;
+    Frag ac[4], an[4];
+    if (steps > 0 && ng > 0) {
+        const T* wr = wrow(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ac[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
     }
-    Frag aA[4], aB[4];
-    if (steps > 0) load_group(aA, 0);
-    for (int st = 0; st < steps; st += 2) {
-        if (st + 1 < steps) load_group(aB, st + 1);
-        step(aA, st);
-        if (st + 1 >= steps) break;
-        if (st + 2 < steps) load_group(aA, st + 2);
-        step(aB, st + 1);
+    for (int st = 0; st < steps; ++st) {
+        const int ui = st / gpu, grp = st - ui * gpu;
+        const int u = wave + ui * nwave;
+        const int nb = u / RG, rg = u - nb * RG;
+        const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
+        if (ng > 0) {
+            if (st + 1 < steps) {
+                const int s1 = st + 1, u1 = s1 / gpu;
+                const T* wr = wrow(u1) + (s1 - u1 * gpu) * GK;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) an[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
+            }
+            const T* xg = xr + grp * GK;
+            // MFMAs element-major over independent accumulators (the NRB row
+            // blocks, or with one row block the four chunk accumulators); the
+            // LDS fragments of chunk q + 1 are read while chunk q multiplies
+            if constexpr (NRB == 1) {
+                Frag b[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[q] = *reinterpret_cast<const Frag*>(xg + q * KCH);
+#pragma unroll
+                for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) mma1(acc[0][q], ac[q], b[q], e);
+            } else {
+                Frag bA[NRB], bB[NRB];
+                auto loadB = [&](Frag (&b)[NRB], int q) {
+#pragma unroll
+                    for (int i = 0; i < NRB; ++i)
+                        b[i] = *reinterpret_cast<const Frag*>(xg + (size_t)i * 16 * ldx + q * KCH);
+                };
+                auto mul = [&](const Frag (&b)[NRB], const Frag& aq) {
+#pragma unroll
+                    for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                        for (int i = 0; i < NRB; ++i) mma1(acc[i][0], aq, b[i], e);
+                };
+                loadB(bA, 0);
+                loadB(bB, 1);
+                mul(bA, ac[0]);
+                loadB(bA, 2);
+                mul(bB, ac[1]);
+                loadB(bB, 3);
+                mul(bA, ac[2]);
+                mul(bB, ac[3]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ac[q] = an[q];
+        }
+        if (grp == gpu - 1) {
+            // remaining K % GK chunks of the unit, then its epilogue
+            if (rem) {
+                const T* wr = wrow(ui) + ng * GK;
+                for (int c = 0; c < rem; ++c) {
+                    const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
+                    Frag b[NRB];
+#pragma unroll
+                    for (int i = 0; i < NRB; ++i)
+                        b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
+#pragma unroll
+                    for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                        for (int i = 0; i < NRB; ++i) mma1(acc[i][0], a, b[i], e);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) {
+                Acc t = acc[i][0];
+#pragma unroll
+                for (int q = 1; q < KS; ++q) t += acc[i][q];
+                epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, t);
+#pragma unroll
+                for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
+            }
+        }
     }
 }
 
@@ -300,14 +295,9 @@ template <int P, int R, class Epi>
 __device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K, int Np,
                                      const typename PT<P>::T* X, int ldx, Epi& epi) {
     constexpr int RB = R / 16;
-    const int nrb = nrb_of<R>(Np);
-    if (nrb == RB) {
-        gemm_units<P, R, RB>(Wm, ldw, K, Np, X, ldx, epi);
-        return;
-    }
-    if constexpr (RB >= 2) {
-        if (nrb == RB / 2) {
-            gemm_units<P, R, RB / 2>(Wm, ldw, K, Np, X, ldx, epi);
+    if constexpr (RB > 1) {
+        if (nrb_of<R>(Np) == RB) {
+            gemm_units<P, R, RB>(Wm, ldw, K, Np, X, ldx, epi);
             return;
         }
     }
@@ -592,20 +582,18 @@ template <int P, int R>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
                                          int out_w, int in_w, int NI, int NJ, const int2* mw, int kbase,
                                          typename PT<P>::A* part) {
+    // 2 x 2 blocks per unit (a single column block works too: the second is
+    // clamped and past in_w); BF16 layers wide enough for every wave take
+    // 4 x 2 for more operand reuse
     if constexpr (R % PT<P>::KCH == 0) {
-        const int nwave = (int)(blockDim.x >> 6);
         const int nwr = (in_w + 31) >> 5;
-        if (NJ >= 2) {
-            if constexpr (P != 0) {
-                if ((NI / 4) * (NJ / 2) >= nwave) {
-                    dw_dense_units<P, R, 4, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
-                    return;
-                }
+        if constexpr (P == 2) {
+            if ((NI / 4) * ((NJ + 1) / 2) >= (int)(blockDim.x >> 6)) {
+                dw_dense_units<P, R, 4, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+                return;
             }
-            dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
-        } else {
-            dw_dense_units<P, R, 2, 1>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
         }
+        dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
     }
 }
 
