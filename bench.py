@@ -32,20 +32,25 @@ PEAK = {  # MI355X dense peaks
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 
 
-def algorithmic_flops(w, offs=None):
+def algorithmic_flops(w, part=None):
     """Flops one gradient evaluation of every chain must do: forward products,
     adjoint products down to the lowest layer holding a selected entry, and
     2 * rows per selected entry (the masked weight gradient).  DeepONet adds
-    the combination G = B T^T and its two adjoint products."""
+    the combination G = B T^T and its two adjoint products dB = dG T and
+    dT = dG^T B.  part: None for the whole gradient; for DeepONet "branch"
+    (branch tower, G and dB: the branch kernel's work) or "trunk" (trunk
+    tower and dT)."""
     total = 0.0
     for c in range(w.n_chains):
         idx = w.chain_idx(c)
         if w.kind == "mlp":
-            towers = [(w.widths_a, w.x.shape[0], 0)]
+            towers = [(w.widths_a, w.x.shape[0], 0, "branch")]
         else:
             nb = sum(w.widths_a[i] * w.widths_a[i + 1] + w.widths_a[i + 1] for i in range(len(w.widths_a) - 1))
-            towers = [(w.widths_a, w.u.shape[0], 0), (w.widths_b, w.yq.shape[0], nb)]
-        for widths, rows, flat0 in towers:
+            towers = [(w.widths_a, w.u.shape[0], 0, "branch"), (w.widths_b, w.yq.shape[0], nb, "trunk")]
+        for widths, rows, flat0, name in towers:
+            if part is not None and name != part:
+                continue
             starts, pos = [], flat0
             for i in range(len(widths) - 1):
                 starts.append(pos)
@@ -59,7 +64,8 @@ def algorithmic_flops(w, offs=None):
             total += 2.0 * rows * sum(sel)                                  # masked weight gradient
         if w.kind == "deeponet":
             nu, nq, p = w.u.shape[0], w.yq.shape[0], w.widths_a[-1]
-            total += 3 * 2.0 * nu * nq * p
+            ncomb = {None: 3, "branch": 2, "trunk": 1}[part]
+            total += ncomb * 2.0 * nu * nq * p
     return total
 
 
@@ -71,9 +77,95 @@ def recorded_traffic(kernel, workload):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
+    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256") == _kernel_sha() else None
+
+
+KERNEL_OF = {"mlp": "k_mlp_grad", "deeponet": "k_branch_grad"}
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_{w} -o bench -- "
+             "python bench.py --config {w} --steps 20 --warmup 2 --adapt 20 --no-cpu-baseline --no-ess",
+    "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE_{w} -o bench -- "
+                  "python bench.py --config {w} --steps 2 --warmup 1 --adapt 2 --no-cpu-baseline --no-ess --timing-reps 5",
+    "WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_WRITE_SIZE_{w} -o bench -- "
+                  "python bench.py --config {w} --steps 2 --warmup 1 --adapt 2 --no-cpu-baseline --no-ess --timing-reps 5",
+    "copy": "rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_copy_{c} -o copy -- python -c \"import torch; "
+            "a=torch.ones(64*2**20, device='cuda'); b=torch.empty_like(a); torch.cuda.synchronize(); b.copy_(a); "
+            "torch.cuda.synchronize()\"",
+}
+COPY_BYTES = 64 * 2 ** 20 * 4
+
+
+def _kernel_sha():
     src = os.path.join(ROOT, "paper_2507_14652_amd", "csrc", "hmc_kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256") == h else None
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+
+
+def _pmc_mean(csv_path, counter, name_part):
+    """Mean per dispatch of `counter` over the kernels whose name contains
+    name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch count."""
+    import csv
+    vals = []
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {name_part} in {csv_path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Writes profiles/<kernel>_<workload>_traffic.json: the dominant kernel's
+    HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the counter reads for a plain device copy of known size."""
+    import glob
+    import workloads
+    kind = workloads.make(workload, n_chains=1).kind
+    kern = KERNEL_OF[kind]
+    one = lambda d: glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    fk, nd = _pmc_mean(one(fetch_dir), "FETCH_SIZE", kern + "<")
+    wk, _ = _pmc_mean(one(write_dir), "WRITE_SIZE", kern + "<")
+    cf, _ = _pmc_mean(one(copy_fetch_dir), "FETCH_SIZE", "copy")
+    cw, _ = _pmc_mean(one(copy_write_dir), "WRITE_SIZE", "copy")
+    ff, wf = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
+    out = {
+        "kernel": kern, "workload": workload, "kernel_source_sha256": _kernel_sha(),
+        "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": nd,
+        "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                             "fetch_factor": ff, "write_factor": wf},
+        "traffic_bytes_per_launch": (fk * ff + wk * wf) * 1024,
+        "commands": ["export TMPDIR=/tmp",
+                     PROFILE_CMDS["FETCH_SIZE"].format(w=workload), PROFILE_CMDS["WRITE_SIZE"].format(w=workload),
+                     PROFILE_CMDS["copy"].format(c="FETCH_SIZE"), PROFILE_CMDS["copy"].format(c="WRITE_SIZE")],
+    }
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_traffic.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["traffic_bytes_per_launch"])
+
+
+def record_trace(workload, trace_dir, bench_json=None):
+    """Writes profiles/<kernel>_<workload>_kernel_trace.txt from the
+    rocprofv3 --stats summary of the benchmark command."""
+    import glob
+    import workloads
+    w = workloads.make(workload)
+    kern = KERNEL_OF[w.kind]
+    stats = open(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0]).read().strip()
+    net = (f"MLP {'-'.join(map(str, w.widths_a))}" if w.kind == "mlp" else
+           f"DeepONet branch {'-'.join(map(str, w.widths_a))}, trunk {'-'.join(map(str, w.widths_b))}")
+    lines = [f"Kernel-trace summary: masked full-batch HMC, workload {workload}",
+             f"({net} tanh, {w.n_rows()} rows, {w.n_chains} chains, {w.nnz // w.n_chains} of {w.n_params} "
+             f"parameters sampled per chain on average, {w.precision.upper()}, L={w.L})",
+             f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
+             "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
+             "  " + PROFILE_CMDS["trace"].format(w=workload), "", "bench_kernel_stats.csv:", stats, ""]
+    if bench_json:
+        b = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
+        lines.append(f"HIP-event mean of {kern} measured inside bench.py in the same run: "
+                     f"{b['kernel_ms']['grad_main']:.4f} ms (kernel_ms.grad_main).")
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_kernel_trace.txt")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path)
 
 
 def cpu_baseline(w, budget_s):
@@ -272,7 +364,17 @@ def main():
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the profiles/ traffic summary for --config from rocprofv3 counter runs and exit")
+    ap.add_argument("--record-trace", nargs="+", metavar="TRACE_DIR [BENCH_LOG]",
+                    help="write the profiles/ kernel-trace summary for --config and exit")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.config, *args.record_traffic)
+        return
+    if args.record_trace:
+        record_trace(args.config, *args.record_trace[:2])
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); chains are independent and would "
               "shard across GPUs with no per-step exchange, which this build does not run.", file=sys.stderr)
@@ -303,14 +405,18 @@ def main():
 
     # dominant kernel, timed alone with HIP events on the engine's stream
     ms = s.time_kernels(args.timing_reps)
-    flops = algorithmic_flops(w)
+    flops = algorithmic_flops(w, None if w.kind == "mlp" else "branch")
     dom_ms = ms[0]
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAK[DTYPE[w.precision]]
-    kname = "k_mlp_grad" if w.kind == "mlp" else "k_branch_grad"
+    kname = KERNEL_OF[w.kind]
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": recorded_traffic(kname, w.name), "kernel": kname,
             "kernel_ms": dom_ms, "flops_per_launch": flops}
+    # the whole gradient evaluation: every tile kernel plus the partial sums
+    grad_ms = sum(ms)
+    grad_tf = algorithmic_flops(w) / (grad_ms * 1e-3) / 1e12
+    gradient = {"kernels_ms": grad_ms, "achieved": grad_tf, "unit": "TFLOP/s", "frac": grad_tf / peak}
 
     acc = float(stats["accepted"].mean())
     line = {
@@ -334,6 +440,7 @@ def main():
         "acceptance": acc,
         "kernel_ms": {"grad_main": ms[0], "trunk_fwd": ms[1], "trunk_bwd": ms[2], "reduce": ms[3]},
         "roofline": roof,
+        "gradient_roofline": gradient,
     }
     s.close()
     if not args.no_ess and w.kind == "mlp":

@@ -309,13 +309,26 @@ __device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K
 // consecutive output columns n0 and the four accumulators.
 
 // Hidden layer: a = tanh(z + b), stored in the product precision.
+// tanh of an activation that is stored in BF16: 1 - 2 / (e^{2x} + 1) with the
+// hardware exponential and reciprocal.  Its absolute error (about 1e-7, from
+// the cancellation near 0) is far below the BF16 rounding of the result
+// (2^-9 relative) except for |x| < 1e-4, whose contributions are as small.
+// The limits come out right: e^{2x} overflows to inf (result 1) or
+// underflows to 0 (result -1).
+__device__ __forceinline__ float tanh_bf16(float x) {
+    return 1.0f - __fdividef(2.0f, __expf(2.0f * x) + 1.0f);
+}
+
 template <int P> struct EpiTanh {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const A* bias; T* out; int ld;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
         typename PT<P>::O4 o;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[v] = (T)act_tanh((A)acc[v] + bias[n0 + v]);
+        for (int v = 0; v < 4; ++v) {
+            if constexpr (P == 2) o[v] = (T)tanh_bf16(acc[v] + bias[n0 + v]);
+            else o[v] = (T)act_tanh((A)acc[v] + bias[n0 + v]);
+        }
         *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
     }
 };
@@ -504,7 +517,7 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
 // before the products and their latency hides behind the MFMAs.  The
 // operands sit row-major in LDS, so each lane reads its K values (one per
 // tile row) one scalar at a time; BI x BJ blocks per wave reuse them.
-// BJ is 1 or 2: the two column blocks of a unit share one bitmap word.
+// BJ = 2: the unit's two column blocks share one bitmap word.
 template <int P, int R, int BI, int BJ>
 __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
                                                int lx, int out_w, int in_w, int NI, int NJ,
@@ -514,13 +527,23 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     typedef typename PT<P>::Acc Acc;
     typedef typename PT<P>::Frag Frag;
     constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
-    static_assert(BJ == 1 || BJ == 2, "one bitmap word per unit row");
+    static_assert(BJ == 2, "a unit's two column blocks share one bitmap word");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
     const int UI = (NI + BI - 1) / BI, UJ = (NJ + BJ - 1) / BJ;
     const int imax = NI * 16 - 1, jmax = NJ * 16 - 1;
     const int nwave = (int)(blockDim.x >> 6);
+    // The lane's column bit in the unit's bitmap word depends only on the
+    // lane and the column block (a unit's first column is a multiple of 32).
+    // Bits are set only inside the layer, so a set bit also says the entry
+    // is in range.
+    unsigned selb[BJ], lowm[BJ];
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+        selb[bj] = 1u << ((unsigned)(bj * 16 + li) & 31u);
+        lowm[bj] = selb[bj] - 1u;
+    }
     for (int u = wave; u < UI * UJ; u += nwave) {
         const int ui = u / UJ, uj = u - ui * UJ;
         const int w = (uj * BJ * 16) >> 5;          // bitmap word of the unit's columns
@@ -563,17 +586,12 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 #pragma unroll
         for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < BJ; ++bj) {
-                const int j = (uj * BJ + bj) * 16 + li;
-                const unsigned bit = (unsigned)j & 31u;
+            for (int v = 0; v < 4; ++v) {
+                const unsigned bits = (unsigned)tw[bi][v].x;
+                const int k0 = kbase + tw[bi][v].y;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const unsigned bits = (unsigned)tw[bi][v].x;
-                    if (j < in_w && ((bits >> bit) & 1u)) {
-                        const int k = kbase + tw[bi][v].y + __popc(bits & ((1u << bit) - 1u));
-                        part[k] = (A)acc[bi][bj][v];
-                    }
-                }
+                for (int bj = 0; bj < BJ; ++bj)
+                    if (bits & selb[bj]) part[k0 + __popc(bits & lowm[bj])] = (A)acc[bi][bj][v];
             }
     }
 }
