@@ -19,13 +19,19 @@ What it computes, in the paper's terms:
   * ``philox``: the counter-based Philox4x64-10 generator (Salmon et al.,
     SC'11) with Box-Muller normals, used for the momentum refresh and the
     Metropolis uniform so that both sides can draw the same numbers.
+  * ``sensitivity``: the parameter sensitivities S_i^2 of Sec. 3.1 (the
+    first-order variance share of each parameter around the VI mean,
+    averaged over the training inputs) and the threshold rule that picks the
+    sensitive subset, from explicit Jacobian rows.
 
 Readings of points the paper leaves open (each is named where it is used):
   K = p^T M^-1 p / 2 (the text calls K the Gaussian log-density of p);
   leapfrog, kick-drift-kick; acceptance compared in log space, non-finite
   energies rejected; likelihood summed over every output entry of the full
   training set with its constant dropped; prior on the selected entries only;
-  M = I unless a diagonal M^-1 is given.
+  M = I unless a diagonal M^-1 is given; for vector outputs the squared
+  output derivatives are summed over output entries and averaged over
+  inputs; ties in the sensitivity order keep index order.
 
 Parity status: every function here is pinned by tests in ``tests/`` against
 closed forms, invariants, brute force or NumPy's own Philox stream.
