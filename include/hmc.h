@@ -212,6 +212,30 @@ hmc_status hmc_get_info(const hmc_ctx* ctx, hmc_info_t* info);
  * The engine state is unchanged. */
 hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
 
+/* Parameter sensitivities of Sec. 3.1 (sensitivity equation): around the
+ * mean parameters mu = net->theta0, with standard deviations sigma (host,
+ * [n_params], finite, >= 0),
+ *   s2[i] = sigma_i^2 / N_d * sum_{rows j} sum_{outputs o} (dF_mu(x_j)_o / dtheta_i)^2
+ * over the n_rows inputs of data (x; y is not read).  The squared output
+ * derivatives are summed over the output entries of each row (their
+ * variances add).  Every layer runs as MFMA tile products on squared
+ * operands on the device; BF16 networks are evaluated in FP32, FP64 networks
+ * in FP64.  s2: host [n_params] FP64, written on success.  MLP networks only
+ * (a DeepONet returns HMC_EUNSUPPORTED).  net->prior_sd and net->lik_sd must be
+ * valid but are not used.  Synchronous; hip_stream as for hmc_init.  Errors:
+ * HMC_EINVAL (NULL pointers, sizes, negative or non-finite sigma),
+ * HMC_ENOMEM, HMC_EDEVICE; the message is in hmc_last_error(NULL). */
+hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma,
+                           double* s2, void* hip_stream);
+
+/* The sensitive subset of Sec. 3.1 (threshold equation): the parameters
+ * ordered from the most to the least sensitive (equal values in index
+ * order), and the largest count N whose cumulative share of sum(s2) is at
+ * most tau.  s2: host [n] (finite, >= 0, not all zero); tau in [0, 1].
+ * idx: host [n], receives the N selected indices in increasing order (a
+ * mask for hmc_init); *n_sel = N (it may be 0).  Host only. */
+hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel);
+
 /* Waits for queued work and reports deferred device errors. */
 hmc_status hmc_sync(hmc_ctx* ctx);
 

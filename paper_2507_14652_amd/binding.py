@@ -25,7 +25,7 @@ KIND = {"mlp": 0, "deeponet": 1}
 ABI_FUNCTIONS = (
     "hmc_init", "hmc_leapfrog", "hmc_sample", "hmc_grad", "hmc_trajectory", "hmc_momentum",
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
-    "hmc_sync", "hmc_last_error", "hmc_destroy",
+    "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
 )
 
 
@@ -92,6 +92,8 @@ def load():
         "hmc_get_info": [P, POINTER(Info)],
         "hmc_time_kernels": [P, c_int32, POINTER(c_double)],
         "hmc_sync": [P],
+        "hmc_sensitivity": [POINTER(NetDesc), POINTER(DataDesc), POINTER(c_double), POINTER(c_double), P],
+        "hmc_select_mask": [POINTER(c_double), c_int64, c_double, POINTER(c_int64), POINTER(c_int64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -120,6 +122,39 @@ def _ptr_of(buf):
             raise ValueError("tensor must be contiguous")
         return c_void_p(buf.data_ptr())
     return c_void_p(buf.ctypes.data)
+
+
+def sensitivities(*, widths_a, theta0, sigma, x, precision="fp32", stream=None):
+    """S_i^2 of every parameter of an MLP around theta0 with standard
+    deviations sigma, over the rows of x (hmc_sensitivity; FP64 array)."""
+    lib = load()
+    wa = np.ascontiguousarray(widths_a, dtype=np.int32)
+    th0, sg, xa = _f64(theta0), _f64(sigma), _f64(x)
+    if sg.shape != th0.shape:
+        raise ValueError("sigma must have one entry per parameter")
+    net = NetDesc(KIND["mlp"], len(wa), wa.ctypes.data_as(POINTER(c_int32)), 0, None,
+                  _dptr(th0), th0.size, 1.0, 1.0, PRECISION[precision], None)
+    data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+    if stream is None and torch.cuda.is_available():
+        stream = torch.cuda.current_stream().cuda_stream
+    out = np.empty(th0.size, dtype=np.float64)
+    st = lib.hmc_sensitivity(ctypes.byref(net), ctypes.byref(data), _dptr(sg), _dptr(out), c_void_p(stream or None))
+    if st != HMC_OK:
+        raise HMCError(st, lib.hmc_last_error(None).decode())
+    return out
+
+
+def select_mask(s2, tau):
+    """Indices (increasing) of the sensitive subset for threshold tau
+    (hmc_select_mask)."""
+    lib = load()
+    s2 = _f64(s2)
+    idx = np.empty(s2.size, dtype=np.int64)
+    n = c_int64(0)
+    st = lib.hmc_select_mask(_dptr(s2), s2.size, float(tau), idx.ctypes.data_as(POINTER(c_int64)), ctypes.byref(n))
+    if st != HMC_OK:
+        raise HMCError(st, lib.hmc_last_error(None).decode())
+    return idx[:n.value].copy()
 
 
 class Sampler:

@@ -80,6 +80,7 @@ struct hmc_ctx {
     int nt_a = 256, nt_b = 256, nt_a32 = 256, nt_b32 = 256;   // threads per workgroup
     // resident MLP kernel (weights in LDS, several tiles per workgroup)
     bool resident = false;
+    bool force_dense = false;     // sensitivity engines: dense dW (squared terms) on every layer
     int kpt = 0, groups = 0, grid_res = 0;
     size_t lds_res = 0;
     GradArgs ga{};
@@ -576,7 +577,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // FP32 MLP workload it is slower than one tile per workgroup (the tiles of
     // a workgroup run one after another at one workgroup per compute unit), so
     // it is opt-in.
-    if (x->kind == HMC_MLP && x->max_n <= 8 * HMC_NT && std::getenv("HMC_RESIDENT") &&
+    if (x->kind == HMC_MLP && !x->force_dense && x->max_n <= 8 * HMC_NT && std::getenv("HMC_RESIDENT") &&
         !std::strcmp(std::getenv("HMC_RESIDENT"), "1")) {
         const int E = (int)(16 / ts);
         long long wl = 0;
@@ -641,7 +642,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             const bool can = nw > 0 && R % kch == 0;
             const bool autod = prec == HMC_BF16 && tp.w[l] >= 64 && tp.w[l + 1] >= 64 &&
                                nw * thr >= (long long)tp.w[l] * tp.w[l + 1];
-            const bool dense = can && !force_gather && (force_dense || autod);
+            const bool dense = can && !force_gather && (force_dense || autod || x->force_dense);
             dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
         }
     }
@@ -904,9 +905,10 @@ hmc_status trajectory_graph(hmc_ctx* x, int L) {
 
 extern "C" {
 
-hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
-                    uint64_t seed, void* hip_stream) {
-    g_init_error.clear();
+namespace {
+
+hmc_status init_ctx(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                    uint64_t seed, void* hip_stream, bool sens) {
     if (!out) { g_init_error = "out is NULL"; return HMC_EINVAL; }
     *out = nullptr;
     std::string err;
@@ -914,6 +916,7 @@ hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
     if (st != HMC_OK) { g_init_error = err; return st; }
     hmc_ctx* x = new (std::nothrow) hmc_ctx();
     if (!x) { g_init_error = "out of host memory"; return HMC_ENOMEM; }
+    x->force_dense = sens;
     x->kind = net->kind;
     x->prec = net->precision;
     x->A.w.assign(net->widths_a, net->widths_a + net->n_widths_a);
@@ -955,6 +958,97 @@ hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
         return st;
     }
     *out = x;
+    return HMC_OK;
+}
+
+}  // namespace
+
+hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                    uint64_t seed, void* hip_stream) {
+    g_init_error.clear();
+    return init_ctx(out, net, mask, data, seed, hip_stream, false);
+}
+
+hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma, double* s2,
+                           void* hip_stream) {
+    g_init_error.clear();
+    if (!net || !data || !sigma || !s2) { g_init_error = "net, data, sigma and s2 must not be NULL"; return HMC_EINVAL; }
+    if (net->kind != HMC_MLP) {
+        g_init_error = "sensitivities are implemented for MLP networks";
+        return HMC_EUNSUPPORTED;
+    }
+    const int64_t P = net->n_params;
+    if (P < 1 || P > (1ll << 30)) { g_init_error = "n_params out of range"; return HMC_EINVAL; }
+    for (int64_t k = 0; k < P; ++k)
+        if (!std::isfinite(sigma[k]) || sigma[k] < 0.0) { g_init_error = "sigma must be finite and >= 0"; return HMC_EINVAL; }
+    // the whole parameter vector as one chain's mask; BF16 networks run in FP32
+    std::vector<int64_t> offs = {0, P}, idx((size_t)P);
+    for (int64_t k = 0; k < P; ++k) idx[(size_t)k] = k;
+    hmc_net_desc n2 = *net;
+    if (n2.precision == HMC_BF16) n2.precision = HMC_FP32;
+    n2.inv_mass_diag = nullptr;
+    hmc_mask_desc m{1, offs.data(), idx.data(), nullptr};
+    // targets are not used; the engine keeps a zero array in their place
+    hmc_data_desc d2 = *data;
+    std::vector<double> zeros;
+    if (!d2.y && d2.n_rows > 0 && d2.n_rows <= (1ll << 30) && n2.n_widths_a >= 2 && n2.widths_a &&
+        n2.widths_a[n2.n_widths_a - 1] > 0 && n2.widths_a[n2.n_widths_a - 1] <= 4096) {
+        zeros.assign((size_t)d2.n_rows * n2.widths_a[n2.n_widths_a - 1], 0.0);
+        d2.y = zeros.data();
+    }
+    hmc_ctx* x = nullptr;
+    hmc_status st = init_ctx(&x, &n2, &m, &d2, 0, hip_stream, true);
+    if (st != HMC_OK) return st;
+    auto done = [&](hmc_status r) {
+        if (r != HMC_OK) g_init_error = x->err;
+        hmc_destroy(x);
+        return r;
+    };
+    double* acc = (double*)x->dalloc(sizeof(double) * P);
+    double* sig = (double*)x->dalloc(sizeof(double) * P);
+    double* s2d = (double*)x->dalloc(sizeof(double) * P);
+    if (!acc || !sig || !s2d) return done(x->fail(HMC_ENOMEM, "device allocation of the sensitivity buffers failed"));
+    if (hipMemcpyAsync(sig, sigma, sizeof(double) * P, hipMemcpyHostToDevice, x->stream) != hipSuccess)
+        return done(x->fail(HMC_EDEVICE, "copy of sigma failed"));
+    const int d_out = x->A.w.back();
+    const double inv_nd = 1.0 / (double)data->n_rows;
+    for (int o = 0; o < d_out; ++o) {
+        hipError_t e = hmc_launch_mlp_sens(x->prec, x->Ra, x->nt_a, x->ga, o, x->grid_a, x->lds_a, x->stream);
+        if (e == hipSuccess)
+            e = hmc_launch_sens_reduce(x->prec, x->ga.part, x->tiles_a, P, acc, sig, inv_nd,
+                                       o == d_out - 1 ? s2d : nullptr, x->stream);
+        if (e != hipSuccess) return done(x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e)));
+    }
+    hipError_t e = hipMemcpyAsync(s2, s2d, sizeof(double) * P, hipMemcpyDeviceToHost, x->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+    if (e != hipSuccess) return done(x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e)));
+    return done(HMC_OK);
+}
+
+hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel) {
+    g_init_error.clear();
+    if (!s2 || !idx || !n_sel || n < 1) { g_init_error = "s2, idx and n_sel must not be NULL and n >= 1"; return HMC_EINVAL; }
+    if (!(tau >= 0.0 && tau <= 1.0)) { g_init_error = "tau must lie in [0, 1]"; return HMC_EINVAL; }
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(s2[k]) || s2[k] < 0.0) { g_init_error = "sensitivities must be finite and >= 0"; return HMC_EINVAL; }
+    // most sensitive first, equal values in index order
+    std::vector<int64_t> ord((size_t)n);
+    for (int64_t k = 0; k < n; ++k) ord[(size_t)k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return s2[a] > s2[b]; });
+    double total = 0.0;
+    for (int64_t k = 0; k < n; ++k) total += s2[ord[(size_t)k]];
+    if (!(total > 0.0)) { g_init_error = "the sensitivities sum to zero"; return HMC_EINVAL; }
+    // the largest count whose cumulative share is at most tau
+    int64_t cnt = 0;
+    double cum = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        cum += s2[ord[(size_t)k]];
+        if (cum / total <= tau) cnt = k + 1;
+        else break;
+    }
+    std::sort(ord.begin(), ord.begin() + cnt);
+    std::copy(ord.begin(), ord.begin() + cnt, idx);
+    *n_sel = cnt;
     return HMC_OK;
 }
 

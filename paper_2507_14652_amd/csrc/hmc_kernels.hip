@@ -461,7 +461,14 @@ template <int P> struct EpiCombine {
 // few entries gives each entry LPE adjacent lanes (rows r = sub mod LPE,
 // then a fixed butterfly over the LPE lanes), so that short segments do not
 // leave most of the workgroup idle behind one R-long chain per entry.
-template <int P, int R>
+// SQ: the sums of squared per-row terms, delta^2 a^2 and delta^2 (the
+// Jacobian square sums of the sensitivity pass).
+template <bool SQ, class V> __device__ __forceinline__ V sq_if(V v) {
+    if constexpr (SQ) return v * v;
+    else return v;
+}
+
+template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0, int k1,
                                             const typename PT<P>::T* D, int ld,
                                             const typename PT<P>::T* X, int lx,
@@ -479,10 +486,10 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
             A s = (A)0;
             if (j == 0xFFFF) {
 #pragma unroll 8
-                for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
+                for (int r = 0; r < R; ++r) s += sq_if<SQ>((A)D[r * ld + i]);
             } else {
 #pragma unroll 8
-                for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+                for (int r = 0; r < R; ++r) s = fma(sq_if<SQ>((A)D[r * ld + i]), sq_if<SQ>((A)X[r * lx + j]), s);
             }
             part[k] = s;
         }
@@ -496,9 +503,9 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
         const int cd = code[k0 + e];
         const int i = cd >> 16, j = cd & 0xFFFF;
         if (j == 0xFFFF) {
-            for (int r = sub; r < R; r += lpe) s += (A)D[r * ld + i];
+            for (int r = sub; r < R; r += lpe) s += sq_if<SQ>((A)D[r * ld + i]);
         } else {
-            for (int r = sub; r < R; r += lpe) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+            for (int r = sub; r < R; r += lpe) s = fma(sq_if<SQ>((A)D[r * ld + i]), sq_if<SQ>((A)X[r * lx + j]), s);
         }
     }
     for (int o = 1; o < lpe; o <<= 1) s += __shfl_xor(s, o, 64);
@@ -518,7 +525,7 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
 // operands sit row-major in LDS, so each lane reads its K values (one per
 // tile row) one scalar at a time; BI x BJ blocks per wave reuse them.
 // BJ = 2: the unit's two column blocks share one bitmap word.
-template <int P, int R, int BI, int BJ>
+template <int P, int R, int BI, int BJ, bool SQ = false>
 __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
                                                int lx, int out_w, int in_w, int NI, int NJ,
                                                const int2* __restrict__ mw, int nwr, int kbase,
@@ -572,9 +579,9 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
 #pragma unroll
-                for (int bi = 0; bi < BI; ++bi) a[bi][e] = D[(r0 + e) * ld + ic[bi]];
+                for (int bi = 0; bi < BI; ++bi) a[bi][e] = sq_if<SQ>(D[(r0 + e) * ld + ic[bi]]);
 #pragma unroll
-                for (int bj = 0; bj < BJ; ++bj) b[bj][e] = X[(r0 + e) * lx + jc[bj]];
+                for (int bj = 0; bj < BJ; ++bj) b[bj][e] = sq_if<SQ>(X[(r0 + e) * lx + jc[bj]]);
             }
 #pragma unroll
             for (int e = 0; e < NE<P>; ++e)
@@ -596,7 +603,7 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     }
 }
 
-template <int P, int R>
+template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
                                          int out_w, int in_w, int NI, int NJ, const int2* mw, int kbase,
                                          typename PT<P>::A* part) {
@@ -607,11 +614,11 @@ __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, con
         const int nwr = (in_w + 31) >> 5;
         if constexpr (P == 2) {
             if ((NI / 4) * ((NJ + 1) / 2) >= (int)(blockDim.x >> 6)) {
-                dw_dense_units<P, R, 4, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+                dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
                 return;
             }
         }
-        dw_dense_units<P, R, 2, 2>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+        dw_dense_units<P, R, 2, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
     }
 }
 
@@ -651,8 +658,9 @@ __device__ __forceinline__ void ulik_store(double* slot8, double v) {
 // Adjoint pass of one tower from the output adjoint held in slab nl: for each
 // layer from the top, the selected weight-gradient partials, then (while a
 // lower layer still has selected entries) the adjoint of the layer input.
-// lowest: lowest_layer() of the chain.
-template <int P, int R>
+// lowest: lowest_layer() of the chain.  SQ: squared weight-gradient terms
+// (sensitivity pass).
+template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, int c, int t,
                                                const typename PT<P>::T* W, typename PT<P>::T* sm, int lowest) {
     typedef typename PT<P>::A A;
@@ -665,12 +673,14 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     const int* dflag = a.dflag + (size_t)c * a.nl_total + tp.seg0;
     for (int l = tp.nl - 1; l >= lowest; --l) {
         if (dflag[l]) {
-            dw_dense<P, R>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
-                           tp.wp[l + 1] >> 4, tp.wp[l] >> 4,
-                           a.mw + a.mw_off[(size_t)c * a.nl_total + tp.seg0 + l], seg[l], part);
-            dw_partials<P, R>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+            dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
+                               tp.wp[l + 1] >> 4, tp.wp[l] >> 4,
+                               a.mw + a.mw_off[(size_t)c * a.nl_total + tp.seg0 + l], seg[l], part);
+            dw_partials<P, R, SQ>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
+                                  part);
         } else {
-            dw_partials<P, R>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], part);
+            dw_partials<P, R, SQ>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
+                                  part);
         }
         if (l > lowest) {
             __syncthreads();
@@ -719,6 +729,56 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
         __syncthreads();
         tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
     }
+}
+
+// MLP sensitivity tile (Sec. 3.1): forward at the mean parameters, then a
+// unit output adjoint for output o on the tile's valid rows, and the adjoint
+// pass with squared weight-gradient terms for every layer:
+//   part[k] = sum_{tile rows} (dF_o/dtheta_k)^2,
+// since for a weight dF_o/dW_l[i][j] = delta_l[i] a_{l-1}[j] on each row and
+// for a bias delta_l[i].  The mask is the whole parameter vector.
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_mlp_sens(const GradArgs a, int o) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    int c, t;
+    if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    T* so = sm + tp.lo[L + 1];
+    const int wpo = tp.wp[L + 1], nv = min(R, a.n_rows_a - t * R);
+    for (int i = threadIdx.x; i < R * wpo; i += blockDim.x) {
+        const int r = i / wpo, col = i - r * wpo;
+        so[r * tp.ls[L + 1] + col] = (col == o && r < nv) ? (T)1 : (T)0;
+    }
+    __syncthreads();
+    tower_backward<P, R, true>(a, tp, c, t, W, sm, 0);
+}
+
+// Sum of the sensitivity partials over the row tiles, in tile order, into an
+// FP64 accumulator (one pass per output); the last pass writes
+// S^2[k] = sigma_k^2 * acc[k] / n_d.
+template <int P>
+__global__ __launch_bounds__(256) void k_sens_reduce(const void* part, int tiles, long long n, double* acc,
+                                                     const double* sigma, double inv_nd, double* s2) {
+    typedef typename PT<P>::A A;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const A* pp = reinterpret_cast<const A*>(part) + k;
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += (double)pp[(size_t)t * n];
+    const double v = acc[k] + s;
+    acc[k] = v;
+    if (s2) s2[k] = sigma[k] * sigma[k] * v * inv_nd;
 }
 
 // Resident MLP kernel for networks whose weights fit in LDS beside the
@@ -1224,6 +1284,9 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if constexpr (P != 2) {
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    }
     if constexpr (P == 1) {
         if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_branch_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
@@ -1249,6 +1312,25 @@ hipError_t set_lds(size_t lds) {
         case 0: CALL(0); case 1: CALL(1); case 2: CALL(2);                     \
         default: return hipErrorInvalidValue;                                  \
     }
+
+hipError_t hmc_launch_mlp_sens(int P, int R, int nt, const GradArgs& a, int o, int grid, size_t lds, hipStream_t s) {
+#define C_(p, r) hipLaunchKernelGGL((k_mlp_sens<p, r>), dim3(grid), dim3(nt), lds, s, a, o); return hipGetLastError()
+    switch (P * 100 + R) {
+        case 16: C_(0, 16); case 32: C_(0, 32); case 64: C_(0, 64);
+        case 116: C_(1, 16); case 132: C_(1, 32); case 164: C_(1, 64);
+        default: return hipErrorInvalidValue;
+    }
+#undef C_
+}
+
+hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, double* acc, const double* sigma,
+                                  double inv_nd, double* s2, hipStream_t s) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (P == 0) hipLaunchKernelGGL((k_sens_reduce<0>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
+    else if (P == 1) hipLaunchKernelGGL((k_sens_reduce<1>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t hmc_set_lds_limit(int P, int R, size_t lds) {
 #define C_(p, r) return set_lds<p, r>(lds)

@@ -13,6 +13,9 @@ hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int gri
 hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_sens(int P, int R, int nt, const GradArgs& a, int o, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, double* acc, const double* sigma,
+                                  double inv_nd, double* s2, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
 hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);

@@ -99,3 +99,49 @@ def test_calls_on_a_null_engine_are_rejected():
     assert lib.hmc_sync(None) == binding.HMC_EINVAL
     assert lib.hmc_grad(None, None, None) == binding.HMC_EINVAL
     lib.hmc_destroy(None)
+
+
+@needs_lib
+@pytest.mark.parametrize("seed,n,tau", [(0, 1, 0.5), (1, 50, 0.9), (2, 1000, 0.3), (3, 1000, 1.0), (4, 7, 0.0)])
+def test_select_mask_matches_the_oracle(seed, n, tau):
+    """The library's threshold selection (host code) against the oracle's,
+    including ties (values drawn from a small set)."""
+    from oracle import sensitivity as osen
+    rng = np.random.default_rng(seed)
+    s2 = rng.choice([0.0, 0.5, 1.0, 2.0, 3.5], size=n) * (1 + (seed % 2) * rng.random(n))
+    s2[0] = max(s2[0], 1.0)
+    got = binding.select_mask(s2, tau)
+    np.testing.assert_array_equal(got, osen.select_mask(s2, tau))
+
+
+@needs_lib
+@pytest.mark.parametrize("s2,tau", [([0.0, 0.0], 0.5), ([1.0, -1.0], 0.5), ([1.0, float("nan")], 0.5),
+                                   ([1.0, 2.0], 1.5), ([1.0, 2.0], -0.1)])
+def test_select_mask_rejects_bad_input(s2, tau):
+    with pytest.raises(binding.HMCError) as e:
+        binding.select_mask(np.array(s2), tau)
+    assert e.value.status == binding.HMC_EINVAL
+
+
+@needs_lib
+def test_sensitivity_rejects_bad_input_on_the_host():
+    lib = binding.load()
+    B = binding
+    wa = np.array([2, 3, 1], dtype=np.int32)
+    theta0 = np.zeros(13)
+    x = np.zeros((5, 2))
+    out = np.zeros(13)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    data = B.DataDesc(dp(x), None, 5, None, None, None, 0, 0)
+
+    def call(kind=0, sigma=np.ones(13), s2=out):
+        net = B.NetDesc(kind, len(wa), wa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0, None, dp(theta0), 13,
+                        1.0, 1.0, 1, None)
+        return lib.hmc_sensitivity(ctypes.byref(net), ctypes.byref(data), dp(sigma) if sigma is not None else None,
+                                   dp(s2) if s2 is not None else None, None)
+    assert call(sigma=None) == B.HMC_EINVAL
+    assert call(s2=None) == B.HMC_EINVAL
+    assert call(sigma=-np.ones(13)) == B.HMC_EINVAL
+    assert call(sigma=np.full(13, np.inf)) == B.HMC_EINVAL
+    assert call(kind=1) == B.HMC_EUNSUPPORTED
+    assert "MLP" in lib.hmc_last_error(None).decode()
