@@ -84,6 +84,8 @@ KERNEL_OF = {"mlp": "k_mlp_grad", "deeponet": "k_branch_grad"}
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_{w} -o bench -- "
              "python bench.py --config {w} --steps 20 --warmup 2 --adapt 20 --no-cpu-baseline --no-ess",
+    "trace_sens": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_sens_{w} -o bench -- "
+                  "python bench.py --config {w} --sensitivity --steps 3 --no-cpu-baseline",
     "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE_{w} -o bench -- "
                   "python bench.py --config {w} --steps 2 --warmup 1 --adapt 2 --no-cpu-baseline --no-ess --timing-reps 5",
     "WRITE_SIZE": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_WRITE_SIZE_{w} -o bench -- "
@@ -143,29 +145,82 @@ def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_di
     print(path, out["traffic_bytes_per_launch"])
 
 
-def record_trace(workload, trace_dir, bench_json=None):
+def record_trace(workload, trace_dir, bench_json=None, sens=False):
     """Writes profiles/<kernel>_<workload>_kernel_trace.txt from the
-    rocprofv3 --stats summary of the benchmark command."""
+    rocprofv3 --stats summary of the benchmark command (sens: of the
+    sensitivity-pass command)."""
     import glob
     import workloads
     w = workloads.make(workload)
-    kern = KERNEL_OF[w.kind]
+    kern = "k_mlp_sens" if sens else KERNEL_OF[w.kind]
     stats = open(glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0]).read().strip()
     net = (f"MLP {'-'.join(map(str, w.widths_a))}" if w.kind == "mlp" else
            f"DeepONet branch {'-'.join(map(str, w.widths_a))}, trunk {'-'.join(map(str, w.widths_b))}")
-    lines = [f"Kernel-trace summary: masked full-batch HMC, workload {workload}",
-             f"({net} tanh, {w.n_rows()} rows, {w.n_chains} chains, {w.nnz // w.n_chains} of {w.n_params} "
-             f"parameters sampled per chain on average, {w.precision.upper()}, L={w.L})",
-             f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
+    if sens:
+        head = [f"Kernel-trace summary: parameter sensitivity pass (Sec. 3.1), workload {workload}",
+                f"({net} tanh, {w.n_rows()} rows, all {w.n_params} parameters, "
+                f"{'FP64' if w.precision == 'fp64' else 'FP32'}; one pass per output)"]
+    else:
+        head = [f"Kernel-trace summary: masked full-batch HMC, workload {workload}",
+                f"({net} tanh, {w.n_rows()} rows, {w.n_chains} chains, {w.nnz // w.n_chains} of {w.n_params} "
+                f"parameters sampled per chain on average, {w.precision.upper()}, L={w.L})"]
+    lines = head + [f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
              "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
-             "  " + PROFILE_CMDS["trace"].format(w=workload), "", "bench_kernel_stats.csv:", stats, ""]
-    if bench_json:
+             "  " + PROFILE_CMDS["trace_sens" if sens else "trace"].format(w=workload), "",
+             "bench_kernel_stats.csv:", stats, ""]
+    if bench_json and sens:
+        b = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
+        lines.append(f"The same run's bench line: {json.dumps(b)}")
+    elif bench_json:
         b = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
         lines.append(f"HIP-event mean of {kern} measured inside bench.py in the same run: "
                      f"{b['kernel_ms']['grad_main']:.4f} ms (kernel_ms.grad_main).")
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_kernel_trace.txt")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path)
+
+
+def sensitivity_flops(widths, rows):
+    """Algorithmic flops of one output's sensitivity pass: forward, the data
+    adjoint above the first layer, and the squared weight-gradient product of
+    every weight (2 * rows per weight), over all rows."""
+    mm = [widths[i] * widths[i + 1] for i in range(len(widths) - 1)]
+    return 2.0 * rows * (sum(mm) + sum(mm[1:]) + sum(mm))
+
+
+def sensitivity_bench(config, reps, cpu_budget):
+    """Times hmc_sensitivity (the whole call: engine set-up, one pass per
+    output, reduction, copy back) on a workload's full data, and the oracle
+    on a bounded row sample; prints one JSON line."""
+    import workloads
+    from paper_2507_14652_amd import sensitivities
+    w = workloads.make(config, n_chains=1)
+    sigma = np.full(w.n_params, 0.1)
+    prec = "fp64" if w.precision == "fp64" else "fp32"
+    sensitivities(widths_a=w.widths_a, theta0=w.theta0, sigma=sigma, x=w.x, precision=prec)   # warm-up
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        sensitivities(widths_a=w.widths_a, theta0=w.theta0, sigma=sigma, x=w.x, precision=prec)
+        t.append(time.perf_counter() - t0)
+    dt = float(np.median(t))
+    rows = w.x.shape[0]
+    flops = sensitivity_flops(w.widths_a, rows) * w.widths_a[-1]
+    line = {"metric": "sensitivity pass (rows x parameters)/s", "value": rows * w.n_params / dt,
+            "unit": "row-params/s", "ms_per_call": dt * 1e3, "config": {"workload": config, "rows": rows,
+            "params": w.n_params, "outputs": w.widths_a[-1], "dtype": DTYPE[prec]},
+            "algorithmic_tflops_whole_call": flops / dt / 1e12}
+    if cpu_budget > 0:
+        from oracle import sensitivity as osen
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < cpu_budget and n < rows:
+            k = min(8, rows - n)
+            osen.jacobian_square_sums("mlp", w.widths_a, None, w.theta0, {"x": w.x[n:n + k]})
+            n += k
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": n * w.n_params / el, "unit": "row-params/s", "kind": "oracle",
+                                "sample": f"{n} of {rows} rows"}
+    print(json.dumps(line))
 
 
 def cpu_baseline(w, budget_s):
@@ -364,6 +419,8 @@ def main():
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
+    ap.add_argument("--sensitivity", action="store_true",
+                    help="time the sensitivity pass (Sec. 3.1) on --config's data instead of the sampler")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the profiles/ traffic summary for --config from rocprofv3 counter runs and exit")
     ap.add_argument("--record-trace", nargs="+", metavar="TRACE_DIR [BENCH_LOG]",
@@ -373,7 +430,10 @@ def main():
         record_traffic(args.config, *args.record_traffic)
         return
     if args.record_trace:
-        record_trace(args.config, *args.record_trace[:2])
+        record_trace(args.config, *args.record_trace[:2], sens=args.sensitivity)
+        return
+    if args.sensitivity:
+        sensitivity_bench(args.config, args.steps if args.steps != 200 else 5, 0.0 if args.no_cpu_baseline else 10.0)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); chains are independent and would "

@@ -858,8 +858,13 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     HMC_HIP(x, hipStreamCreateWithFlags(&x->cap_stream, hipStreamNonBlocking));
 
     // Scatter the starting positions and evaluate U and the gradient there.
-    HMC_HIP(x, hmc_launch_scatter_all(prec, s, x->stream));
-    HMC_TRY(launch_refresh(x, x->stream));
+    // A sensitivity engine samples nothing: its weights are theta0 already
+    // (every entry selected, starting at theta0), and it needs neither U nor
+    // the gradient.
+    if (!x->force_dense) {
+        HMC_HIP(x, hmc_launch_scatter_all(prec, s, x->stream));
+        HMC_TRY(launch_refresh(x, x->stream));
+    }
     HMC_HIP(x, hipStreamSynchronize(x->stream));
     return HMC_OK;
 }

@@ -774,8 +774,15 @@ __global__ __launch_bounds__(256) void k_sens_reduce(const void* part, int tiles
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const A* pp = reinterpret_cast<const A*>(part) + k;
-    double s = 0.0;
-    for (int t = 0; t < tiles; ++t) s += (double)pp[(size_t)t * n];
+    // eight independent sums (tiles t = j mod 8) combined in a fixed order
+    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int t = 0;
+    for (; t + 8 <= tiles; t += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] += (double)pp[(size_t)(t + j) * n];
+    }
+    for (int j = 0; t < tiles; ++t, ++j) q[j] += (double)pp[(size_t)t * n];
+    const double s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
     const double v = acc[k] + s;
     acc[k] = v;
     if (s2) s2[k] = sigma[k] * sigma[k] * v * inv_nd;
