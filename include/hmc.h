@@ -228,6 +228,21 @@ hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
 hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma,
                            double* s2, void* hip_stream);
 
+/* Posterior predictive moments (the mean prediction and its spread shown in
+ * the results sections) of chain `chain` over n_samples stored samples:
+ * samples is laid out as hmc_sample writes it, [n_samples][nnz] in the
+ * state type, host or device; sample k of the chain is
+ * samples + k * nnz + offs[chain], its other parameters stay at their fixed
+ * values.  inputs->x [n_rows][d_in] (host) are the new inputs (y is not
+ * read).  mean (host, [n_rows][d_out], required) receives the mean of the
+ * network outputs over the samples and var (host, same shape, or NULL) their
+ * variance (1/n_samples, no Bessel correction), both accumulated in FP64.
+ * BF16 engines evaluate through their FP32 weight shadow.  The engine's
+ * chain state is unchanged.  MLP engines only (a DeepONet engine returns
+ * HMC_EUNSUPPORTED).  Synchronous. */
+hmc_status hmc_predict(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t n_samples,
+                       const hmc_data_desc* inputs, double* mean, double* var);
+
 /* The sensitive subset of Sec. 3.1 (threshold equation): the parameters
  * ordered from the most to the least sensitive (equal values in index
  * order), and the largest count N whose cumulative share of sum(s2) is at

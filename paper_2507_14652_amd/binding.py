@@ -26,6 +26,7 @@ ABI_FUNCTIONS = (
     "hmc_init", "hmc_leapfrog", "hmc_sample", "hmc_grad", "hmc_trajectory", "hmc_momentum",
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
     "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
+    "hmc_predict",
 )
 
 
@@ -94,6 +95,7 @@ def load():
         "hmc_sync": [P],
         "hmc_sensitivity": [POINTER(NetDesc), POINTER(DataDesc), POINTER(c_double), POINTER(c_double), P],
         "hmc_select_mask": [POINTER(c_double), c_int64, c_double, POINTER(c_int64), POINTER(c_int64)],
+        "hmc_predict": [P, c_int32, P, c_int64, POINTER(DataDesc), POINTER(c_double), POINTER(c_double)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -167,6 +169,7 @@ class Sampler:
         self._lib = load()
         self._ctx = c_void_p()
         self.kind = kind
+        self._widths_a = list(widths_a)
         self.precision = precision
         self.state_dtype = torch.float64 if precision == "fp64" else torch.float32
         self._np_state = np.float64 if precision == "fp64" else np.float32
@@ -298,6 +301,27 @@ class Sampler:
         self._check(self._lib.hmc_counters(self._ctx, a.ctypes.data_as(POINTER(c_int64)),
                                            d.ctypes.data_as(POINTER(c_int64))))
         return a, d
+
+    def predict(self, samples, x, chain=0):
+        """Mean and variance (FP64 arrays [rows][d_out]) of the network output
+        at the rows of x over stored samples ([n][nnz], as sample() writes
+        them; torch tensor or NumPy array) of one chain."""
+        xa = _f64(x)
+        if isinstance(samples, torch.Tensor):
+            if samples.dtype != self.state_dtype or samples.dim() != 2 or samples.shape[1] != self.nnz:
+                raise ValueError("samples must be [n][nnz] in the state dtype")
+        else:
+            samples = np.ascontiguousarray(samples, dtype=self._np_state)
+            if samples.ndim != 2 or samples.shape[1] != self.nnz:
+                raise ValueError("samples must be [n][nnz]")
+        d_out = int(self._widths_a[-1])
+        mean = np.empty((xa.shape[0], d_out))
+        var = np.empty_like(mean)
+        data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+        torch.cuda.synchronize()
+        self._check(self._lib.hmc_predict(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]),
+                                          ctypes.byref(data), _dptr(mean), _dptr(var)))
+        return mean, var
 
     def time_kernels(self, reps=20):
         ms = np.zeros(4)

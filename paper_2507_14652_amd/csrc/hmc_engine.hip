@@ -1030,6 +1030,69 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
     return done(HMC_OK);
 }
 
+hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
+                       const hmc_data_desc* inputs, double* mean, double* var) {
+    if (!x) return HMC_EINVAL;
+    if (x->kind != HMC_MLP) return x->fail(HMC_EUNSUPPORTED, "predictions are implemented for MLP networks");
+    if (chain < 0 || chain >= x->C) return x->fail(HMC_EINVAL, "chain out of range");
+    if (!samples || n_samples < 1) return x->fail(HMC_EINVAL, "samples must not be NULL and n_samples >= 1");
+    if (!inputs || !inputs->x || inputs->n_rows < 1 || inputs->n_rows > (1ll << 30))
+        return x->fail(HMC_EINVAL, "inputs need x and 1 <= n_rows <= 2^30");
+    if (!mean) return x->fail(HMC_EINVAL, "mean must not be NULL");
+    // BF16 engines predict through their FP32 weight shadow
+    const bool f32 = x->energy32;
+    const int P = f32 ? (int)HMC_FP32 : x->prec;
+    const GradArgs& gsrc = f32 ? x->ga32 : x->ga;
+    const int R = f32 ? x->Ra32 : x->Ra;
+    const int nt = f32 ? x->nt_a32 : x->nt_a;
+    const size_t lds = f32 ? x->lds_a32 : x->lds_a;
+    const size_t ts = f32 ? 4 : tsize_of(x->prec), ss = ssize_of(x->prec);
+    const long long rows = inputs->n_rows;
+    const int din = x->A.w[0], dout = x->A.w.back(), wp0 = gsrc.ta.wp[0];
+    const int tiles = (int)((rows + R - 1) / R);
+    const long long o = x->offs[chain], nc = x->offs[chain + 1] - o;
+    // new inputs in the tile layout of the training rows (padded rows and widths)
+    std::vector<unsigned char> h((size_t)tiles * R * wp0 * ts, 0);
+    for (long long r = 0; r < rows; ++r)
+        for (int j = 0; j < din; ++j) put_t(h, f32 ? (int)HMC_FP32 : x->prec, (size_t)(r * wp0 + j), inputs->x[r * din + j]);
+    void *xt = nullptr, *stage = nullptr;
+    double* mom = nullptr;   // mean, m2, var
+    const size_t no = (size_t)rows * dout;
+    auto cleanup = [&]() {
+        if (xt) (void)hipFree(xt);
+        if (stage) (void)hipFree(stage);
+        if (mom) (void)hipFree(mom);
+    };
+    if (hipMalloc(&xt, h.size()) != hipSuccess || hipMalloc(&stage, (size_t)nc * ss) != hipSuccess ||
+        hipMalloc((void**)&mom, sizeof(double) * 3 * no) != hipSuccess) {
+        cleanup();
+        return x->fail(HMC_ENOMEM, "device allocation for the predictions failed");
+    }
+    GradArgs g = gsrc;
+    g.xa = xt;
+    g.n_rows_a = (int)rows;
+    g.tiles_a = tiles;
+    hipError_t e = hipMemcpyAsync(xt, h.data(), h.size(), hipMemcpyHostToDevice, x->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(mom, 0, sizeof(double) * 3 * no, x->stream);
+    for (int64_t k = 0; k < n_samples && e == hipSuccess; ++k) {
+        e = hipMemcpyAsync(stage, (const char*)samples + ((size_t)k * x->nnz + o) * ss, (size_t)nc * ss,
+                           hipMemcpyDefault, x->stream);
+        if (e == hipSuccess) e = hmc_launch_scatter_vec(x->prec, x->sa, chain, stage, nc, x->stream);
+        if (e == hipSuccess)
+            e = hmc_launch_mlp_predict(P, R, nt, g, chain, roundup(tiles, 8), lds, x->stream, mom, mom + no,
+                                       k == n_samples - 1 ? mom + 2 * no : nullptr, 1.0 / (double)(k + 1),
+                                       1.0 / (double)n_samples);
+    }
+    // the engine's own positions back into the dense weights
+    if (e == hipSuccess) e = hmc_launch_scatter_all(x->prec, x->sa, x->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(mean, mom, sizeof(double) * no, hipMemcpyDeviceToHost, x->stream);
+    if (e == hipSuccess && var) e = hipMemcpyAsync(var, mom + 2 * no, sizeof(double) * no, hipMemcpyDeviceToHost, x->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+    cleanup();
+    if (e != hipSuccess) return x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
+    return HMC_OK;
+}
+
 hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel) {
     g_init_error.clear();
     if (!s2 || !idx || !n_sel || n < 1) { g_init_error = "s2, idx and n_sel must not be NULL and n >= 1"; return HMC_EINVAL; }

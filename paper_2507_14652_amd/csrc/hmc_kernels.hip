@@ -389,6 +389,32 @@ template <int P> struct EpiMlpHead {
     }
 };
 
+// Posterior predictive head: F = z + b for the valid rows and outputs, folded
+// into FP64 running moments over the samples (Welford: after the k-th
+// sample mean holds the mean of the first k outputs and m2 the sum of their
+// squared deviations); the last sample also writes var = m2 / n.
+template <int P> struct EpiPredict {
+    typedef typename PT<P>::A A;
+    const A* bias; int d_out; int row0; int nrows;
+    double* mean; double* m2; double* var; double inv_k; double inv_n;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        const int row = row0 + r;
+        if (row >= nrows) return;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + v;
+            if (n >= d_out) continue;
+            const size_t i = (size_t)row * d_out + n;
+            const double f = (double)acc[v] + (double)bias[n];
+            const double mu = mean[i], d = f - mu, mu2 = mu + d * inv_k;
+            const double q = m2[i] + d * (f - mu2);
+            mean[i] = mu2;
+            m2[i] = q;
+            if (var) var[i] = q * inv_n;
+        }
+    }
+};
+
 // Branch output layer: B = z + b kept in LDS for the combination, and B^T
 // written to global memory for the trunk adjoint (zero for padded rows).
 template <int P> struct EpiBranchOut {
@@ -762,6 +788,32 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_sens(const GradArgs a, int o) {
     }
     __syncthreads();
     tower_backward<P, R, true>(a, tp, c, t, W, sm, 0);
+}
+
+// Posterior predictive tile: the forward pass of chain c's current dense
+// weights over one tile of new input rows, and the running moments of the
+// outputs (EpiPredict).  a.xa, a.n_rows_a and a.tiles_a describe the new
+// inputs; activation slabs may alias (ping-pong plans).
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_mlp_predict(const GradArgs a, int c, double* mean, double* m2,
+                                                        double* var, double inv_k, double inv_n) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    int c0, t;
+    if (!tile_of(a.tiles_a, a.tiles_a, c0, t)) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    EpiPredict<P> e{B + tp.bo[L], a.d_out, t * R, a.n_rows_a, mean, m2, var, inv_k, inv_n};
+    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], e);
 }
 
 // Sum of the sensitivity partials over the row tiles, in tile order, into an
@@ -1282,6 +1334,18 @@ __global__ __launch_bounds__(256) void k_scatter_all(const StateArgs s) {
         scatter<P>(s, c, o + k, reinterpret_cast<const S*>(s.theta)[o + k]);
 }
 
+// Writes a given position vector of chain c (state type, [n_c]) into the
+// chain's dense weights and biases (all copies), as the drift's scatter does.
+template <int P>
+__global__ __launch_bounds__(256) void k_scatter_vec(const StateArgs s, int c, const void* vec) {
+    typedef typename PT<P>::S S;
+    const long long o = s.offs[c];
+    const long long n = s.offs[c + 1] - o;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    scatter<P>(s, c, o + k, reinterpret_cast<const S*>(vec)[k]);
+}
+
 template <int P, int R>
 hipError_t set_lds(size_t lds) {
     hipError_t e;
@@ -1293,6 +1357,7 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if constexpr (P != 2) {
         if ((e = hipFuncSetAttribute((const void*)k_mlp_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_predict<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     }
     if constexpr (P == 1) {
         if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
@@ -1336,6 +1401,30 @@ hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long 
     if (P == 0) hipLaunchKernelGGL((k_sens_reduce<0>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
     else if (P == 1) hipLaunchKernelGGL((k_sens_reduce<1>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t hmc_launch_mlp_predict(int P, int R, int nt, const GradArgs& a, int c, int grid, size_t lds,
+                                  hipStream_t s, double* mean, double* m2, double* var, double inv_k, double inv_n) {
+#define C_(p, r) hipLaunchKernelGGL((k_mlp_predict<p, r>), dim3(grid), dim3(nt), lds, s, a, c, mean, m2, var, inv_k, \
+                                   inv_n); return hipGetLastError()
+    switch (P * 100 + R) {
+        case 16: C_(0, 16); case 32: C_(0, 32); case 64: C_(0, 64);
+        case 116: C_(1, 16); case 132: C_(1, 32); case 164: C_(1, 64);
+        default: return hipErrorInvalidValue;
+    }
+#undef C_
+}
+
+hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    switch (P) {
+        case 0: hipLaunchKernelGGL((k_scatter_vec<0>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
+        case 1: hipLaunchKernelGGL((k_scatter_vec<1>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
+        case 2: hipLaunchKernelGGL((k_scatter_vec<2>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
