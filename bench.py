@@ -223,6 +223,42 @@ def sensitivity_bench(config, reps, cpu_budget):
     print(json.dumps(line))
 
 
+def predict_bench(config, n_samples, n_new, cpu_budget):
+    """Times hmc_predict (posterior predictive mean and variance of one chain
+    over n_samples stored samples at n_new new inputs, engine set-up
+    excluded) and the oracle on a bounded sample count; prints one JSON
+    line."""
+    import torch
+    import workloads
+    from paper_2507_14652_amd import Sampler
+    w = workloads.make(config)
+    s = Sampler.from_workload(w, seed=5)
+    out = torch.empty((n_samples, w.nnz), dtype=s.state_dtype, device="cuda")
+    s.sample(n_samples, w.eps, w.L, out=out)
+    x_new = np.random.default_rng(3).uniform(w.x.min(axis=0), w.x.max(axis=0), (n_new, w.x.shape[1]))
+    s.predict(out[:2], x_new)                                       # warm-up
+    t0 = time.perf_counter()
+    s.predict(out, x_new)
+    dt = time.perf_counter() - t0
+    mm = [w.widths_a[i] * w.widths_a[i + 1] for i in range(len(w.widths_a) - 1)]
+    flops = 2.0 * n_new * sum(mm) * n_samples
+    line = {"metric": "posterior predictive (samples x rows)/s", "value": n_samples * n_new / dt,
+            "unit": "sample-rows/s", "ms_per_call": dt * 1e3,
+            "config": {"workload": config, "samples": n_samples, "new_rows": n_new, "dtype": DTYPE[w.precision]},
+            "algorithmic_tflops": flops / dt / 1e12}
+    if cpu_budget > 0:
+        from oracle import predictive as opr
+        S = out.double().cpu().numpy()[:, w.offs[0]:w.offs[1]]
+        k, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < cpu_budget and k < n_samples:
+            opr.predictive_moments("mlp", w.widths_a, None, w.theta0, w.chain_idx(0), S[k:k + 1], {"x": x_new})
+            k += 1
+        line["cpu_baseline"] = {"value": k * n_new / (time.perf_counter() - t0), "unit": "sample-rows/s",
+                                "kind": "oracle", "sample": f"{k} of {n_samples} samples"}
+    s.close()
+    print(json.dumps(line))
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle on the host cores: gradient evaluations per second,
     summed over the chains it ran, on a bounded sample of the workload."""
@@ -419,6 +455,8 @@ def main():
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
+    ap.add_argument("--predict", action="store_true",
+                    help="time the posterior predictive (200 samples of chain 0 at 4096 new inputs) on --config")
     ap.add_argument("--sensitivity", action="store_true",
                     help="time the sensitivity pass (Sec. 3.1) on --config's data instead of the sampler")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -431,6 +469,9 @@ def main():
         return
     if args.record_trace:
         record_trace(args.config, *args.record_trace[:2], sens=args.sensitivity)
+        return
+    if args.predict:
+        predict_bench(args.config, 200, 4096, 0.0 if args.no_cpu_baseline else 10.0)
         return
     if args.sensitivity:
         sensitivity_bench(args.config, args.steps if args.steps != 200 else 5, 0.0 if args.no_cpu_baseline else 10.0)

@@ -215,16 +215,21 @@ hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
 /* Parameter sensitivities of Sec. 3.1 (sensitivity equation): around the
  * mean parameters mu = net->theta0, with standard deviations sigma (host,
  * [n_params], finite, >= 0),
- *   s2[i] = sigma_i^2 / N_d * sum_{rows j} sum_{outputs o} (dF_mu(x_j)_o / dtheta_i)^2
- * over the n_rows inputs of data (x; y is not read).  The squared output
- * derivatives are summed over the output entries of each row (their
- * variances add).  Every layer runs as MFMA tile products on squared
- * operands on the device; BF16 networks are evaluated in FP32, FP64 networks
- * in FP64.  s2: host [n_params] FP64, written on success.  MLP networks only
- * (a DeepONet returns HMC_EUNSUPPORTED).  net->prior_sd and net->lik_sd must be
- * valid but are not used.  Synchronous; hip_stream as for hmc_init.  Errors:
- * HMC_EINVAL (NULL pointers, sizes, negative or non-finite sigma),
- * HMC_ENOMEM, HMC_EDEVICE; the message is in hmc_last_error(NULL). */
+ *   s2[i] = sigma_i^2 / N_d * sum_{inputs j} sum_{outputs o} (dF_mu(x_j)_o / dtheta_i)^2.
+ * MLP: the n_rows rows of data->x are the inputs, the outputs of a row its
+ * output entries (y is not read).  DeepONet: the n_u functions of data->u are
+ * the inputs, the n_q query points of data->yq the outputs of each (v is not
+ * read).  The squared output derivatives are summed over the output entries
+ * of each input (their variances add).  Every layer runs as MFMA tile
+ * products on squared operands on the device, one adjoint pass per output
+ * (MLP), per query point (DeepONet branch, seeded with the trunk features)
+ * and per function (DeepONet trunk, seeded with the branch features); BF16
+ * networks are evaluated in FP32, FP64 networks in FP64.  s2: host
+ * [n_params] FP64, written on success.  net->prior_sd and net->lik_sd must
+ * be valid but are not used.  Synchronous; hip_stream as for hmc_init.
+ * Errors: HMC_EINVAL (NULL pointers, sizes, negative or non-finite sigma),
+ * HMC_ENOMEM, HMC_EDEVICE, HMC_EUNSUPPORTED (a tower that does not fit in
+ * LDS); the message is in hmc_last_error(NULL). */
 hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma,
                            double* s2, void* hip_stream);
 

@@ -126,21 +126,33 @@ def _ptr_of(buf):
     return c_void_p(buf.ctypes.data)
 
 
-def sensitivities(*, widths_a, theta0, sigma, x, precision="fp32", stream=None):
-    """S_i^2 of every parameter of an MLP around theta0 with standard
-    deviations sigma, over the rows of x (hmc_sensitivity; FP64 array)."""
+def sensitivities(*, widths_a, theta0, sigma, x=None, kind="mlp", widths_b=None, u=None, yq=None,
+                  precision="fp32", stream=None):
+    """S_i^2 of every parameter around theta0 with standard deviations sigma
+    (hmc_sensitivity; FP64 array): an MLP over the rows of x, or a DeepONet
+    over the functions u and query points yq."""
     lib = load()
     wa = np.ascontiguousarray(widths_a, dtype=np.int32)
-    th0, sg, xa = _f64(theta0), _f64(sigma), _f64(x)
+    wb = np.ascontiguousarray(widths_b if widths_b is not None else [0], dtype=np.int32)
+    th0, sg = _f64(theta0), _f64(sigma)
     if sg.shape != th0.shape:
         raise ValueError("sigma must have one entry per parameter")
-    net = NetDesc(KIND["mlp"], len(wa), wa.ctypes.data_as(POINTER(c_int32)), 0, None,
+    net = NetDesc(KIND[kind], len(wa), wa.ctypes.data_as(POINTER(c_int32)),
+                  len(wb) if widths_b is not None else 0, wb.ctypes.data_as(POINTER(c_int32)),
                   _dptr(th0), th0.size, 1.0, 1.0, PRECISION[precision], None)
-    data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+    if kind == "mlp":
+        xa = _f64(x)
+        keep = [xa]
+        data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+    else:
+        ua, qa = _f64(u), _f64(yq)
+        keep = [ua, qa]
+        data = DataDesc(None, None, 0, _dptr(ua), _dptr(qa), None, ua.shape[0], qa.shape[0])
     if stream is None and torch.cuda.is_available():
         stream = torch.cuda.current_stream().cuda_stream
     out = np.empty(th0.size, dtype=np.float64)
     st = lib.hmc_sensitivity(ctypes.byref(net), ctypes.byref(data), _dptr(sg), _dptr(out), c_void_p(stream or None))
+    del keep
     if st != HMC_OK:
         raise HMCError(st, lib.hmc_last_error(None).decode())
     return out

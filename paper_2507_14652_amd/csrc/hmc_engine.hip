@@ -978,10 +978,7 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
                            void* hip_stream) {
     g_init_error.clear();
     if (!net || !data || !sigma || !s2) { g_init_error = "net, data, sigma and s2 must not be NULL"; return HMC_EINVAL; }
-    if (net->kind != HMC_MLP) {
-        g_init_error = "sensitivities are implemented for MLP networks";
-        return HMC_EUNSUPPORTED;
-    }
+    if (net->kind != HMC_MLP && net->kind != HMC_DEEPONET) { g_init_error = "kind must be MLP or DeepONet"; return HMC_EINVAL; }
     const int64_t P = net->n_params;
     if (P < 1 || P > (1ll << 30)) { g_init_error = "n_params out of range"; return HMC_EINVAL; }
     for (int64_t k = 0; k < P; ++k)
@@ -996,10 +993,14 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
     // targets are not used; the engine keeps a zero array in their place
     hmc_data_desc d2 = *data;
     std::vector<double> zeros;
-    if (!d2.y && d2.n_rows > 0 && d2.n_rows <= (1ll << 30) && n2.n_widths_a >= 2 && n2.widths_a &&
-        n2.widths_a[n2.n_widths_a - 1] > 0 && n2.widths_a[n2.n_widths_a - 1] <= 4096) {
+    if (n2.kind == HMC_MLP && !d2.y && d2.n_rows > 0 && d2.n_rows <= (1ll << 30) && n2.n_widths_a >= 2 &&
+        n2.widths_a && n2.widths_a[n2.n_widths_a - 1] > 0 && n2.widths_a[n2.n_widths_a - 1] <= 4096) {
         zeros.assign((size_t)d2.n_rows * n2.widths_a[n2.n_widths_a - 1], 0.0);
         d2.y = zeros.data();
+    }
+    if (n2.kind == HMC_DEEPONET && !d2.v && d2.n_u > 0 && d2.n_q > 0 && d2.n_u <= (1ll << 24) && d2.n_q <= (1ll << 24)) {
+        zeros.assign((size_t)d2.n_u * d2.n_q, 0.0);
+        d2.v = zeros.data();
     }
     hmc_ctx* x = nullptr;
     hmc_status st = init_ctx(&x, &n2, &m, &d2, 0, hip_stream, true);
@@ -1009,22 +1010,57 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
         hmc_destroy(x);
         return r;
     };
+    const size_t ts = tsize_of(x->prec);
+    const int la = (int)x->A.w.size() - 1;
+    const int wpo = x->ga.ta.wp[la];
+    const bool deep = x->kind == HMC_DEEPONET;
+    const long long rows_a = deep ? data->n_u : data->n_rows, rows_b = deep ? data->n_q : 0;
     double* acc = (double*)x->dalloc(sizeof(double) * P);
     double* sig = (double*)x->dalloc(sizeof(double) * P);
     double* s2d = (double*)x->dalloc(sizeof(double) * P);
-    if (!acc || !sig || !s2d) return done(x->fail(HMC_ENOMEM, "device allocation of the sensitivity buffers failed"));
-    if (hipMemcpyAsync(sig, sigma, sizeof(double) * P, hipMemcpyHostToDevice, x->stream) != hipSuccess)
-        return done(x->fail(HMC_EDEVICE, "copy of sigma failed"));
-    const int d_out = x->A.w.back();
-    const double inv_nd = 1.0 / (double)data->n_rows;
-    for (int o = 0; o < d_out; ++o) {
-        hipError_t e = hmc_launch_mlp_sens(x->prec, x->Ra, x->nt_a, x->ga, o, x->grid_a, x->lds_a, x->stream);
+    // seeds: MLP, the unit vectors of the outputs; DeepONet, the trunk
+    // features T_q (branch passes) and the branch features B_j (trunk passes)
+    const long long nseed_a = deep ? rows_b : x->A.w.back();
+    void* seed_a = x->dalloc((size_t)nseed_a * wpo * ts);
+    void* seed_b = deep ? x->dalloc((size_t)rows_a * wpo * ts) : nullptr;
+    if (!acc || !sig || !s2d || !seed_a || (deep && !seed_b))
+        return done(x->fail(HMC_ENOMEM, "device allocation of the sensitivity buffers failed"));
+    hipError_t e = hipMemcpyAsync(sig, sigma, sizeof(double) * P, hipMemcpyHostToDevice, x->stream);
+    const int P_ = x->prec;
+    const GradArgs& g = x->ga;
+    if (!deep) {
+        std::vector<unsigned char> h((size_t)nseed_a * wpo * ts, 0);
+        for (long long o = 0; o < nseed_a; ++o) put_t(h, P_, (size_t)(o * wpo + o), 1.0);
+        if (e == hipSuccess) e = hipMemcpyAsync(seed_a, h.data(), h.size(), hipMemcpyHostToDevice, x->stream);
+        for (long long o = 0; o < nseed_a && e == hipSuccess; ++o) {
+            e = hmc_launch_tower_sens(P_, x->Ra, x->nt_a, g, 0, (const char*)seed_a + (size_t)o * wpo * ts, x->grid_a,
+                                      x->lds_a, x->stream);
+            if (e == hipSuccess)
+                e = hmc_launch_sens_reduce(P_, g.part, x->tiles_a, P, 0, P, acc, sig, 1.0 / (double)rows_a,
+                                           o == nseed_a - 1 ? s2d : nullptr, x->stream);
+        }
+    } else {
+        const long long nb = x->B.flat0;   // entries of the branch tower come first, b0 last
+        if (e == hipSuccess) e = hmc_launch_tower_out(P_, x->Rb, x->nt_b, g, 1, seed_a, wpo, x->grid_b, x->lds_b, x->stream);
+        if (e == hipSuccess) e = hmc_launch_tower_out(P_, x->Ra, x->nt_a, g, 0, seed_b, wpo, x->grid_a, x->lds_a, x->stream);
+        for (long long q = 0; q < rows_b && e == hipSuccess; ++q) {
+            e = hmc_launch_tower_sens(P_, x->Ra, x->nt_a, g, 0, (const char*)seed_a + (size_t)q * wpo * ts, x->grid_a,
+                                      x->lds_a, x->stream);
+            if (e == hipSuccess) e = hmc_launch_sens_reduce(P_, g.part, x->tiles_a, P, 0, nb, acc, sig, 0.0, nullptr, x->stream);
+        }
+        for (long long j = 0; j < rows_a && e == hipSuccess; ++j) {
+            e = hmc_launch_tower_sens(P_, x->Rb, x->nt_b, g, 1, (const char*)seed_b + (size_t)j * wpo * ts, x->grid_b,
+                                      x->lds_b, x->stream);
+            if (e == hipSuccess)
+                e = hmc_launch_sens_reduce(P_, g.part, x->tiles_b, P, nb, P - 1, acc, sig, 0.0, nullptr, x->stream);
+        }
+        // dF/db0 = 1 on every (function, query point) entry
+        const double nb0 = (double)rows_a * (double)rows_b;
+        if (e == hipSuccess) e = hipMemcpyAsync(acc + (P - 1), &nb0, sizeof(double), hipMemcpyHostToDevice, x->stream);
         if (e == hipSuccess)
-            e = hmc_launch_sens_reduce(x->prec, x->ga.part, x->tiles_a, P, acc, sig, inv_nd,
-                                       o == d_out - 1 ? s2d : nullptr, x->stream);
-        if (e != hipSuccess) return done(x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e)));
+            e = hmc_launch_sens_reduce(P_, g.part, 0, P, 0, P, acc, sig, 1.0 / (double)rows_a, s2d, x->stream);
     }
-    hipError_t e = hipMemcpyAsync(s2, s2d, sizeof(double) * P, hipMemcpyDeviceToHost, x->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s2, s2d, sizeof(double) * P, hipMemcpyDeviceToHost, x->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
     if (e != hipSuccess) return done(x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e)));
     return done(HMC_OK);

@@ -757,37 +757,108 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     }
 }
 
-// MLP sensitivity tile (Sec. 3.1): forward at the mean parameters, then a
-// unit output adjoint for output o on the tile's valid rows, and the adjoint
-// pass with squared weight-gradient terms for every layer:
-//   part[k] = sum_{tile rows} (dF_o/dtheta_k)^2,
-// since for a weight dF_o/dW_l[i][j] = delta_l[i] a_{l-1}[j] on each row and
-// for a bias delta_l[i].  The mask is the whole parameter vector.
+// Sensitivity tile of one tower (Sec. 3.1): the forward pass at the mean
+// parameters through the hidden layers, then the output adjoint set to the
+// same seed vector on every valid row of the tile (its other rows zero), and
+// the adjoint pass with squared weight-gradient terms on every layer:
+//   part[k] = sum_{tile rows} (seed . dout/dtheta_k)^2,
+// since per row dF/dW_l[i][j] = delta_l[i] a_{l-1}[j] and dF/db_l[i] =
+// delta_l[i] for the output F = seed . out.  MLP: seed e_o for output o.
+// DeepONet: F_jq = <B_j, T_q> + b0, so the branch tower with seed T_q gives
+// the terms of query point q and the trunk tower with seed B_j those of
+// function j.  tower 0: the MLP or branch tower (a.ta, a.xa), 1: the trunk
+// (a.tb, a.xb).  seed: product type, [wp_out], device.
 template <int P, int R>
-__global__ __launch_bounds__(HMC_NT) void k_mlp_sens(const GradArgs a, int o) {
+__global__ __launch_bounds__(HMC_NT) void k_tower_sens(const GradArgs a, int tower, const void* seed) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
+    const int tiles = tower ? a.tiles_b : a.tiles_a;
     int c, t;
-    if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
-    const TowerPlan& tp = a.ta;
+    if (!tile_of(a.n_chains * tiles, tiles, c, t)) return;
+    const TowerPlan& tp = tower ? a.tb : a.ta;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
     const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
     const int L = tp.nl - 1;
-    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    A* Bs = reinterpret_cast<A*>(smem + (tower ? a.bias_lds_b : a.bias_lds_a));
     stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
     const A* B = Bs - tp.bo[0];
-    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    const T* xin = reinterpret_cast<const T*>(tower ? a.xb : a.xa);
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], xin + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
     tower_hidden_forward<P, R>(tp, W, B, sm);
     T* so = sm + tp.lo[L + 1];
-    const int wpo = tp.wp[L + 1], nv = min(R, a.n_rows_a - t * R);
+    const T* sv = reinterpret_cast<const T*>(seed);
+    const int wpo = tp.wp[L + 1], nv = min(R, (tower ? a.n_rows_b : a.n_rows_a) - t * R);
     for (int i = threadIdx.x; i < R * wpo; i += blockDim.x) {
         const int r = i / wpo, col = i - r * wpo;
-        so[r * tp.ls[L + 1] + col] = (col == o && r < nv) ? (T)1 : (T)0;
+        so[r * tp.ls[L + 1] + col] = r < nv ? sv[col] : (T)0;
     }
     __syncthreads();
     tower_backward<P, R, true>(a, tp, c, t, W, sm, 0);
+}
+
+// Output of one tower at the current weights for the rows of its tile,
+// out[row][n] = (W_L a_{L-1} + b_L)[n] for the valid rows (product type,
+// row stride ld): the DeepONet features that seed the sensitivity passes.
+template <int P> struct EpiRowsOut {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const A* bias; T* out; int ld; int row0; int nrows;
+    __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
+        if (row0 + r >= nrows) return;
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = (T)((A)acc[v] + bias[n0 + v]);
+        *reinterpret_cast<typename PT<P>::O4*>(out + (size_t)(row0 + r) * ld + n0) = o;
+    }
+};
+
+template <int P, int R>
+__global__ __launch_bounds__(HMC_NT) void k_tower_out(const GradArgs a, int tower, void* out, int ld) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    const int tiles = tower ? a.tiles_b : a.tiles_a;
+    int c, t;
+    if (!tile_of(a.n_chains * tiles, tiles, c, t)) return;
+    const TowerPlan& tp = tower ? a.tb : a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    A* Bs = reinterpret_cast<A*>(smem + (tower ? a.bias_lds_b : a.bias_lds_a));
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    const A* B = Bs - tp.bo[0];
+    const T* xin = reinterpret_cast<const T*>(tower ? a.xb : a.xa);
+    load_rows<T, R>(sm + tp.lo[0], tp.ls[0], xin + (size_t)t * R * tp.wp[0], tp.wp[0]);
+    __syncthreads();
+    tower_hidden_forward<P, R>(tp, W, B, sm);
+    EpiRowsOut<P> e{B + tp.bo[L], reinterpret_cast<T*>(out), ld, t * R, tower ? a.n_rows_b : a.n_rows_a};
+    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], e);
+}
+
+// Sum of the sensitivity partials of entries [k0, k1) over the row tiles,
+// in tile order, into an FP64 accumulator (one pass per seed); a pass with
+// s2 set also writes S^2[k] = sigma_k^2 * acc[k] / n_d.
+template <int P>
+__global__ __launch_bounds__(256) void k_sens_reduce(const void* part, int tiles, long long n, long long k0,
+                                                     long long k1, double* acc, const double* sigma, double inv_nd,
+                                                     double* s2) {
+    typedef typename PT<P>::A A;
+    const long long k = k0 + (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= k1) return;
+    const A* pp = reinterpret_cast<const A*>(part) + k;
+    // eight independent sums (tiles t = j mod 8) combined in a fixed order
+    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int t = 0;
+    for (; t + 8 <= tiles; t += 8) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) q[jj] += (double)pp[(size_t)(t + jj) * n];
+    }
+    for (int jj = 0; t < tiles; ++t, ++jj) q[jj] += (double)pp[(size_t)t * n];
+    const double sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    const double v = acc[k] + sum;
+    acc[k] = v;
+    if (s2) s2[k] = sigma[k] * sigma[k] * v * inv_nd;
 }
 
 // Posterior predictive tile: the forward pass of chain c's current dense
@@ -816,29 +887,6 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_predict(const GradArgs a, int c,
     gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], e);
 }
 
-// Sum of the sensitivity partials over the row tiles, in tile order, into an
-// FP64 accumulator (one pass per output); the last pass writes
-// S^2[k] = sigma_k^2 * acc[k] / n_d.
-template <int P>
-__global__ __launch_bounds__(256) void k_sens_reduce(const void* part, int tiles, long long n, double* acc,
-                                                     const double* sigma, double inv_nd, double* s2) {
-    typedef typename PT<P>::A A;
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    const A* pp = reinterpret_cast<const A*>(part) + k;
-    // eight independent sums (tiles t = j mod 8) combined in a fixed order
-    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int t = 0;
-    for (; t + 8 <= tiles; t += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) q[j] += (double)pp[(size_t)(t + j) * n];
-    }
-    for (int j = 0; t < tiles; ++t, ++j) q[j] += (double)pp[(size_t)t * n];
-    const double s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-    const double v = acc[k] + s;
-    acc[k] = v;
-    if (s2) s2[k] = sigma[k] * sigma[k] * v * inv_nd;
-}
 
 // Resident MLP kernel for networks whose weights fit in LDS beside the
 // activation slabs.  One workgroup per (chain, group of tpw row tiles):
@@ -1356,7 +1404,8 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if constexpr (P != 2) {
-        if ((e = hipFuncSetAttribute((const void*)k_mlp_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_tower_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_tower_out<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_mlp_predict<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     }
     if constexpr (P == 1) {
@@ -1385,8 +1434,10 @@ hipError_t set_lds(size_t lds) {
         default: return hipErrorInvalidValue;                                  \
     }
 
-hipError_t hmc_launch_mlp_sens(int P, int R, int nt, const GradArgs& a, int o, int grid, size_t lds, hipStream_t s) {
-#define C_(p, r) hipLaunchKernelGGL((k_mlp_sens<p, r>), dim3(grid), dim3(nt), lds, s, a, o); return hipGetLastError()
+hipError_t hmc_launch_tower_sens(int P, int R, int nt, const GradArgs& a, int tower, const void* seed, int grid,
+                                 size_t lds, hipStream_t s) {
+#define C_(p, r) hipLaunchKernelGGL((k_tower_sens<p, r>), dim3(grid), dim3(nt), lds, s, a, tower, seed); \
+    return hipGetLastError()
     switch (P * 100 + R) {
         case 16: C_(0, 16); case 32: C_(0, 32); case 64: C_(0, 64);
         case 116: C_(1, 16); case 132: C_(1, 32); case 164: C_(1, 64);
@@ -1395,11 +1446,26 @@ hipError_t hmc_launch_mlp_sens(int P, int R, int nt, const GradArgs& a, int o, i
 #undef C_
 }
 
-hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, double* acc, const double* sigma,
-                                  double inv_nd, double* s2, hipStream_t s) {
-    const unsigned g = (unsigned)((n + 255) / 256);
-    if (P == 0) hipLaunchKernelGGL((k_sens_reduce<0>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
-    else if (P == 1) hipLaunchKernelGGL((k_sens_reduce<1>), dim3(g), dim3(256), 0, s, part, tiles, n, acc, sigma, inv_nd, s2);
+hipError_t hmc_launch_tower_out(int P, int R, int nt, const GradArgs& a, int tower, void* out, int ld, int grid,
+                                size_t lds, hipStream_t s) {
+#define C_(p, r) hipLaunchKernelGGL((k_tower_out<p, r>), dim3(grid), dim3(nt), lds, s, a, tower, out, ld); \
+    return hipGetLastError()
+    switch (P * 100 + R) {
+        case 16: C_(0, 16); case 32: C_(0, 32); case 64: C_(0, 64);
+        case 116: C_(1, 16); case 132: C_(1, 32); case 164: C_(1, 64);
+        default: return hipErrorInvalidValue;
+    }
+#undef C_
+}
+
+hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, long long k0, long long k1,
+                                  double* acc, const double* sigma, double inv_nd, double* s2, hipStream_t s) {
+    const unsigned g = (unsigned)((k1 - k0 + 255) / 256);
+    if (g == 0) return hipSuccess;
+    if (P == 0)
+        hipLaunchKernelGGL((k_sens_reduce<0>), dim3(g), dim3(256), 0, s, part, tiles, n, k0, k1, acc, sigma, inv_nd, s2);
+    else if (P == 1)
+        hipLaunchKernelGGL((k_sens_reduce<1>), dim3(g), dim3(256), 0, s, part, tiles, n, k0, k1, acc, sigma, inv_nd, s2);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

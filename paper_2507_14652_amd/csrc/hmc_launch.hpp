@@ -13,9 +13,12 @@ hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int gri
 hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_mlp_sens(int P, int R, int nt, const GradArgs& a, int o, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, double* acc, const double* sigma,
-                                  double inv_nd, double* s2, hipStream_t s);
+hipError_t hmc_launch_tower_sens(int P, int R, int nt, const GradArgs& a, int tower, const void* seed, int grid,
+                                 size_t lds, hipStream_t s);
+hipError_t hmc_launch_tower_out(int P, int R, int nt, const GradArgs& a, int tower, void* out, int ld, int grid,
+                                size_t lds, hipStream_t s);
+hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long n, long long k0, long long k1,
+                                  double* acc, const double* sigma, double inv_nd, double* s2, hipStream_t s);
 hipError_t hmc_launch_mlp_predict(int P, int R, int nt, const GradArgs& a, int c, int grid, size_t lds,
                                   hipStream_t s, double* mean, double* m2, double* var, double inv_k, double inv_n);
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s);

@@ -143,5 +143,5 @@ def test_sensitivity_rejects_bad_input_on_the_host():
     assert call(s2=None) == B.HMC_EINVAL
     assert call(sigma=-np.ones(13)) == B.HMC_EINVAL
     assert call(sigma=np.full(13, np.inf)) == B.HMC_EINVAL
-    assert call(kind=1) == B.HMC_EUNSUPPORTED
-    assert "MLP" in lib.hmc_last_error(None).decode()
+    assert call(kind=4) == B.HMC_EINVAL
+    assert "kind" in lib.hmc_last_error(None).decode()

@@ -75,6 +75,28 @@ def test_multi_output_and_ragged_rows(rows):
     _check(got, ref, "fp32")
 
 
+@pytest.mark.parametrize("name,kw,prec", [
+    ("antideriv_deeponet_bf16", dict(n_u=40, n_q=9, n_chains=1), "fp32"),
+    ("antideriv_deeponet_bf16", dict(n_u=70, n_q=23, n_chains=1), "fp64"),
+    ("antideriv_deeponet_bf16", dict(n_u=33, n_q=17, n_chains=1), "bf16"),
+])
+def test_deeponet_sensitivities_match_oracle(name, kw, prec):
+    """Branch passes seeded with the trunk features of each query point,
+    trunk passes with the branch features of each function, b0 in closed
+    form; ragged tiles in both towers."""
+    from paper_2507_14652_amd import sensitivities
+    w = workloads.make(name, **kw)
+    rng = np.random.default_rng(8)
+    sigma = rng.uniform(0.05, 0.3, w.n_params)
+    got = sensitivities(kind="deeponet", widths_a=w.widths_a, widths_b=w.widths_b, theta0=w.theta0, sigma=sigma,
+                        u=w.u, yq=w.yq, precision=prec)
+    ref = osen.sensitivities("deeponet", w.widths_a, w.widths_b, w.theta0, sigma, {"u": w.u, "yq": w.yq})
+    print(f"{name} {prec}: rel {np.linalg.norm(got - ref) / np.linalg.norm(ref):.2e}")
+    _check(got, ref, "fp64" if prec == "fp64" else "fp32")
+    for tau in (0.3, 0.9):
+        assert _same_selection(got, ref, tau)
+
+
 def test_zero_sigma_gives_zero_sensitivity():
     w = workloads.make("regress2d_fp32", n_rows=64)
     sigma = np.full(w.n_params, 0.1)
