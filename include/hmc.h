@@ -238,13 +238,15 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
  * samples is laid out as hmc_sample writes it, [n_samples][nnz] in the
  * state type, host or device; sample k of the chain is
  * samples + k * nnz + offs[chain], its other parameters stay at their fixed
- * values.  inputs->x [n_rows][d_in] (host) are the new inputs (y is not
- * read).  mean (host, [n_rows][d_out], required) receives the mean of the
- * network outputs over the samples and var (host, same shape, or NULL) their
- * variance (1/n_samples, no Bessel correction), both accumulated in FP64.
- * BF16 engines evaluate through their FP32 weight shadow.  The engine's
- * chain state is unchanged.  MLP engines only (a DeepONet engine returns
- * HMC_EUNSUPPORTED).  Synchronous. */
+ * values.  New inputs (host): MLP inputs->x [n_rows][d_in] (y not read),
+ * outputs [n_rows][d_out]; DeepONet inputs->u [n_u][m] and inputs->yq
+ * [n_q][d_y] (v not read), outputs [n_u][n_q].  mean (host, output shape,
+ * required) receives the mean of the network outputs over the samples and
+ * var (host, same shape, or NULL) their variance (1/n_samples, no Bessel
+ * correction), both accumulated in FP64.  BF16 engines evaluate through
+ * their FP32 weight shadow.  The engine's chain state is unchanged.
+ * Synchronous.  Errors: HMC_EINVAL (chain, sizes, NULL pointers), HMC_ENOMEM,
+ * HMC_EDEVICE. */
 hmc_status hmc_predict(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t n_samples,
                        const hmc_data_desc* inputs, double* mean, double* var);
 

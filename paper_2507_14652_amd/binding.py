@@ -314,11 +314,11 @@ class Sampler:
                                            d.ctypes.data_as(POINTER(c_int64))))
         return a, d
 
-    def predict(self, samples, x, chain=0):
-        """Mean and variance (FP64 arrays [rows][d_out]) of the network output
-        at the rows of x over stored samples ([n][nnz], as sample() writes
-        them; torch tensor or NumPy array) of one chain."""
-        xa = _f64(x)
+    def predict(self, samples, x=None, chain=0, u=None, yq=None):
+        """Mean and variance (FP64 arrays) of the network output over stored
+        samples ([n][nnz], as sample() writes them; torch tensor or NumPy
+        array) of one chain: an MLP at the rows of x ([rows][d_out]), a
+        DeepONet at functions u and query points yq ([n_u][n_q])."""
         if isinstance(samples, torch.Tensor):
             if samples.dtype != self.state_dtype or samples.dim() != 2 or samples.shape[1] != self.nnz:
                 raise ValueError("samples must be [n][nnz] in the state dtype")
@@ -326,13 +326,22 @@ class Sampler:
             samples = np.ascontiguousarray(samples, dtype=self._np_state)
             if samples.ndim != 2 or samples.shape[1] != self.nnz:
                 raise ValueError("samples must be [n][nnz]")
-        d_out = int(self._widths_a[-1])
-        mean = np.empty((xa.shape[0], d_out))
-        var = np.empty_like(mean)
-        data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+        if self.kind == "mlp":
+            xa = _f64(x)
+            keep = [xa]
+            shape = (xa.shape[0], int(self._widths_a[-1]))
+            data = DataDesc(_dptr(xa), None, xa.shape[0], None, None, None, 0, 0)
+        else:
+            ua, qa = _f64(u), _f64(yq)
+            keep = [ua, qa]
+            shape = (ua.shape[0], qa.shape[0])
+            data = DataDesc(None, None, 0, _dptr(ua), _dptr(qa), None, ua.shape[0], qa.shape[0])
+        mean = np.empty(shape)
+        var = np.empty(shape)
         torch.cuda.synchronize()
         self._check(self._lib.hmc_predict(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]),
                                           ctypes.byref(data), _dptr(mean), _dptr(var)))
+        del keep
         return mean, var
 
     def time_kernels(self, reps=20):

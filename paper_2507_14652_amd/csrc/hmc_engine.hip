@@ -1069,55 +1069,89 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
 hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
                        const hmc_data_desc* inputs, double* mean, double* var) {
     if (!x) return HMC_EINVAL;
-    if (x->kind != HMC_MLP) return x->fail(HMC_EUNSUPPORTED, "predictions are implemented for MLP networks");
+    const bool deep = x->kind == HMC_DEEPONET;
     if (chain < 0 || chain >= x->C) return x->fail(HMC_EINVAL, "chain out of range");
     if (!samples || n_samples < 1) return x->fail(HMC_EINVAL, "samples must not be NULL and n_samples >= 1");
-    if (!inputs || !inputs->x || inputs->n_rows < 1 || inputs->n_rows > (1ll << 30))
-        return x->fail(HMC_EINVAL, "inputs need x and 1 <= n_rows <= 2^30");
+    if (!inputs) return x->fail(HMC_EINVAL, "inputs must not be NULL");
+    if (!deep && (!inputs->x || inputs->n_rows < 1 || inputs->n_rows > (1ll << 30)))
+        return x->fail(HMC_EINVAL, "MLP inputs need x and 1 <= n_rows <= 2^30");
+    if (deep && (!inputs->u || !inputs->yq || inputs->n_u < 1 || inputs->n_q < 1 || inputs->n_u > (1ll << 24) ||
+                 inputs->n_q > (1ll << 24)))
+        return x->fail(HMC_EINVAL, "DeepONet inputs need u, yq and 1 <= n_u, n_q <= 2^24");
     if (!mean) return x->fail(HMC_EINVAL, "mean must not be NULL");
     // BF16 engines predict through their FP32 weight shadow
     const bool f32 = x->energy32;
     const int P = f32 ? (int)HMC_FP32 : x->prec;
-    const GradArgs& gsrc = f32 ? x->ga32 : x->ga;
-    const int R = f32 ? x->Ra32 : x->Ra;
-    const int nt = f32 ? x->nt_a32 : x->nt_a;
-    const size_t lds = f32 ? x->lds_a32 : x->lds_a;
-    const size_t ts = f32 ? 4 : tsize_of(x->prec), ss = ssize_of(x->prec);
-    const long long rows = inputs->n_rows;
-    const int din = x->A.w[0], dout = x->A.w.back(), wp0 = gsrc.ta.wp[0];
-    const int tiles = (int)((rows + R - 1) / R);
+    GradArgs g = f32 ? x->ga32 : x->ga;
+    const int Ra = f32 ? x->Ra32 : x->Ra, Rb = f32 ? x->Rb32 : x->Rb;
+    const int nta = f32 ? x->nt_a32 : x->nt_a, ntb = f32 ? x->nt_b32 : x->nt_b;
+    const size_t ldsa = f32 ? x->lds_a32 : x->lds_a, ldsb = f32 ? x->lds_b32 : x->lds_b;
+    const size_t ts = f32 ? 4 : tsize_of(x->prec), ss = ssize_of(x->prec), as = asize_of(x->prec);
     const long long o = x->offs[chain], nc = x->offs[chain + 1] - o;
     // new inputs in the tile layout of the training rows (padded rows and widths)
-    std::vector<unsigned char> h((size_t)tiles * R * wp0 * ts, 0);
-    for (long long r = 0; r < rows; ++r)
-        for (int j = 0; j < din; ++j) put_t(h, f32 ? (int)HMC_FP32 : x->prec, (size_t)(r * wp0 + j), inputs->x[r * din + j]);
-    void *xt = nullptr, *stage = nullptr;
-    double* mom = nullptr;   // mean, m2, var
-    const size_t no = (size_t)rows * dout;
-    auto cleanup = [&]() {
-        if (xt) (void)hipFree(xt);
-        if (stage) (void)hipFree(stage);
-        if (mom) (void)hipFree(mom);
+    auto tiled = [&](const double* src, long long rows, int w, int wp, int R, std::vector<unsigned char>& h) {
+        const long long tiles = (rows + R - 1) / R;
+        h.assign((size_t)tiles * R * wp * ts, 0);
+        for (long long r = 0; r < rows; ++r)
+            for (int k = 0; k < w; ++k) put_t(h, P, (size_t)(r * wp + k), src[r * w + k]);
+        return (int)tiles;
     };
-    if (hipMalloc(&xt, h.size()) != hipSuccess || hipMalloc(&stage, (size_t)nc * ss) != hipSuccess ||
-        hipMalloc((void**)&mom, sizeof(double) * 3 * no) != hipSuccess) {
+    const long long ra = deep ? inputs->n_u : inputs->n_rows, rb = deep ? inputs->n_q : 0;
+    const int la = (int)x->A.w.size() - 1;
+    const int wpo = g.ta.wp[la];
+    const size_t no = deep ? (size_t)ra * rb : (size_t)ra * x->A.w.back();
+    std::vector<unsigned char> ha, hb;
+    const int tiles_a = tiled(deep ? inputs->u : inputs->x, ra, x->A.w[0], g.ta.wp[0], Ra, ha);
+    const int tiles_b = deep ? tiled(inputs->yq, rb, x->B.w[0], g.tb.wp[0], Rb, hb) : 0;
+    std::vector<void*> tmp;
+    auto dev = [&](size_t bytes) -> void* {
+        void* d = nullptr;
+        if (hipMalloc(&d, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        tmp.push_back(d);
+        return d;
+    };
+    auto cleanup = [&]() { for (void* d : tmp) (void)hipFree(d); };
+    void* xa = dev(ha.size());
+    void* xb = deep ? dev(hb.size()) : nullptr;
+    void* stage = dev((size_t)nc * ss);
+    double* mom = (double*)dev(sizeof(double) * 3 * no);   // mean, m2, var
+    void* Bn = deep ? dev((size_t)ra * wpo * ts) : nullptr;
+    void* Tn = deep ? dev((size_t)rb * wpo * ts) : nullptr;
+    if (!xa || !stage || !mom || (deep && (!xb || !Bn || !Tn))) {
         cleanup();
         return x->fail(HMC_ENOMEM, "device allocation for the predictions failed");
     }
-    GradArgs g = gsrc;
-    g.xa = xt;
-    g.n_rows_a = (int)rows;
-    g.tiles_a = tiles;
-    hipError_t e = hipMemcpyAsync(xt, h.data(), h.size(), hipMemcpyHostToDevice, x->stream);
+    // one chain's weights as a one-chain argument set over the new inputs
+    g.wbuf = (const char*)g.wbuf + (size_t)chain * g.wstride * ts;
+    g.bbuf = (const char*)g.bbuf + (size_t)chain * g.bstride * as;
+    g.n_chains = 1;
+    g.xa = xa;
+    g.n_rows_a = (int)ra;
+    g.tiles_a = tiles_a;
+    g.xb = xb;
+    g.n_rows_b = (int)rb;
+    g.tiles_b = tiles_b;
+    const void* b0 = (const char*)g.bbuf + (size_t)g.b0_off * as;
+    hipError_t e = hipMemcpyAsync(xa, ha.data(), ha.size(), hipMemcpyHostToDevice, x->stream);
+    if (e == hipSuccess && deep) e = hipMemcpyAsync(xb, hb.data(), hb.size(), hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess) e = hipMemsetAsync(mom, 0, sizeof(double) * 3 * no, x->stream);
     for (int64_t k = 0; k < n_samples && e == hipSuccess; ++k) {
+        const double inv_k = 1.0 / (double)(k + 1), inv_n = 1.0 / (double)n_samples;
+        double* vout = k == n_samples - 1 ? mom + 2 * no : nullptr;
         e = hipMemcpyAsync(stage, (const char*)samples + ((size_t)k * x->nnz + o) * ss, (size_t)nc * ss,
                            hipMemcpyDefault, x->stream);
         if (e == hipSuccess) e = hmc_launch_scatter_vec(x->prec, x->sa, chain, stage, nc, x->stream);
-        if (e == hipSuccess)
-            e = hmc_launch_mlp_predict(P, R, nt, g, chain, roundup(tiles, 8), lds, x->stream, mom, mom + no,
-                                       k == n_samples - 1 ? mom + 2 * no : nullptr, 1.0 / (double)(k + 1),
-                                       1.0 / (double)n_samples);
+        if (e != hipSuccess) break;
+        if (!deep) {
+            e = hmc_launch_mlp_predict(P, Ra, nta, g, 0, roundup(tiles_a, 8), ldsa, x->stream, mom, mom + no, vout,
+                                       inv_k, inv_n);
+        } else {
+            e = hmc_launch_tower_out(P, Rb, ntb, g, 1, Tn, wpo, roundup(tiles_b, 8), ldsb, x->stream);
+            if (e == hipSuccess) e = hmc_launch_tower_out(P, Ra, nta, g, 0, Bn, wpo, roundup(tiles_a, 8), ldsa, x->stream);
+            if (e == hipSuccess)
+                e = hmc_launch_combine_predict(P, Bn, Tn, wpo, x->A.w.back(), ra, rb, b0, mom, mom + no, vout, inv_k,
+                                               inv_n, x->stream);
+        }
     }
     // the engine's own positions back into the dense weights
     if (e == hipSuccess) e = hmc_launch_scatter_all(x->prec, x->sa, x->stream);

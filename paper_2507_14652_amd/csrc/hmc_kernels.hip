@@ -1382,6 +1382,30 @@ __global__ __launch_bounds__(256) void k_scatter_all(const StateArgs s) {
         scatter<P>(s, c, o + k, reinterpret_cast<const S*>(s.theta)[o + k]);
 }
 
+// DeepONet posterior predictive combination: G[j][q] = <B_j, T_q> + b0 from
+// the tower outputs of the new functions (Bn, [n_u][ld]) and query points
+// (Tn, [n_q][ld]), products accumulated in the accumulator type, folded into
+// the FP64 running moments as EpiPredict does.  One thread per (j, q).
+template <int P>
+__global__ __launch_bounds__(256) void k_combine_predict(const void* Bn, const void* Tn, int ld, int p, long long nu,
+                                                         long long nq, const void* b0, double* mean, double* m2,
+                                                         double* var, double inv_k, double inv_n) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nu * nq) return;
+    const long long j = i / nq, q = i - j * nq;
+    const T* b = reinterpret_cast<const T*>(Bn) + (size_t)j * ld;
+    const T* t = reinterpret_cast<const T*>(Tn) + (size_t)q * ld;
+    A s = (A)0;
+    for (int k = 0; k < p; ++k) s = fma((A)b[k], (A)t[k], s);
+    const double f = (double)s + (double)*reinterpret_cast<const A*>(b0);
+    const double mu = mean[i], d = f - mu, mu2 = mu + d * inv_k;
+    const double qq = m2[i] + d * (f - mu2);
+    mean[i] = mu2;
+    m2[i] = qq;
+    if (var) var[i] = qq * inv_n;
+}
+
 // Writes a given position vector of chain c (state type, [n_c]) into the
 // chain's dense weights and biases (all copies), as the drift's scatter does.
 template <int P>
@@ -1480,6 +1504,20 @@ hipError_t hmc_launch_mlp_predict(int P, int R, int nt, const GradArgs& a, int c
         default: return hipErrorInvalidValue;
     }
 #undef C_
+}
+
+hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int ld, int p, long long nu, long long nq,
+                                     const void* b0, double* mean, double* m2, double* var, double inv_k,
+                                     double inv_n, hipStream_t s) {
+    const unsigned g = (unsigned)((nu * nq + 255) / 256);
+    if (P == 0)
+        hipLaunchKernelGGL((k_combine_predict<0>), dim3(g), dim3(256), 0, s, Bn, Tn, ld, p, nu, nq, b0, mean, m2, var,
+                           inv_k, inv_n);
+    else if (P == 1)
+        hipLaunchKernelGGL((k_combine_predict<1>), dim3(g), dim3(256), 0, s, Bn, Tn, ld, p, nu, nq, b0, mean, m2, var,
+                           inv_k, inv_n);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s) {

@@ -21,6 +21,9 @@ hipError_t hmc_launch_sens_reduce(int P, const void* part, int tiles, long long 
                                   double* acc, const double* sigma, double inv_nd, double* s2, hipStream_t s);
 hipError_t hmc_launch_mlp_predict(int P, int R, int nt, const GradArgs& a, int c, int grid, size_t lds,
                                   hipStream_t s, double* mean, double* m2, double* var, double inv_k, double inv_n);
+hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int ld, int p, long long nu, long long nq,
+                                     const void* b0, double* mean, double* m2, double* var, double inv_k,
+                                     double inv_n, hipStream_t s);
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);

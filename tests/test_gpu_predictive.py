@@ -72,12 +72,27 @@ def test_predict_leaves_the_sampler_state_and_accepts_host_samples():
     s.close()
 
 
-def test_predict_on_a_deeponet_engine_is_reported_unsupported():
+@pytest.mark.parametrize("prec,n", [("fp32", 5), ("bf16", 4), ("fp64", 3)])
+def test_deeponet_predictive_moments_match_oracle(prec, n):
+    """New functions and query points (ragged tiles in both towers); the
+    combination G = <B_j, T_q> + b0 over the samples."""
     from paper_2507_14652_amd import Sampler
-    from paper_2507_14652_amd.binding import HMCError, HMC_EUNSUPPORTED
-    w = workloads.make("antideriv_deeponet_bf16", n_u=40, n_q=9, n_chains=1)
-    s = Sampler.from_workload(w, precision="fp32")
-    with pytest.raises(HMCError) as e:
-        s.predict(np.zeros((1, w.nnz), dtype=np.float32), np.zeros((3, 1)))
-    assert e.value.status == HMC_EUNSUPPORTED
+    w = workloads.make("antideriv_deeponet_bf16", n_u=50, n_q=11, n_chains=2)
+    s = Sampler.from_workload(w, precision=prec, seed=4)
+    out = torch.empty((n, w.nnz), dtype=s.state_dtype, device="cuda")
+    s.sample(n, 1e-4, 10, out=out)
+    rng = np.random.default_rng(2)
+    u_new, yq_new = rng.normal(0, 1, (37, w.u.shape[1])), rng.uniform(0, 1, (19, 1))
+    mean, var = s.predict(out, u=u_new, yq=yq_new, chain=1)
+    sl = slice(w.offs[1], w.offs[2])
+    m_ref, v_ref = op.predictive_moments("deeponet", w.widths_a, w.widths_b, w.theta0, w.chain_idx(1),
+                                         out.double().cpu().numpy()[:, sl], {"u": u_new, "yq": yq_new})
+    em = np.linalg.norm(mean - m_ref) / np.linalg.norm(m_ref)
+    print(f"deeponet {prec}: mean rel {em:.2e}, var err {np.abs(var - v_ref).max():.2e} (max {v_ref.max():.2e})")
+    if prec == "fp64":
+        np.testing.assert_allclose(mean, m_ref, rtol=1e-10, atol=1e-12 * np.abs(m_ref).max())
+        np.testing.assert_allclose(var, v_ref, rtol=1e-6, atol=1e-12 * np.max(m_ref ** 2))
+    else:
+        assert em <= 1e-5
+        np.testing.assert_allclose(var, v_ref, rtol=1e-3, atol=1e-7 * np.max(m_ref ** 2))
     s.close()
