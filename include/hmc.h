@@ -155,6 +155,34 @@ typedef struct {
 hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask,
                     const hmc_data_desc* data, uint64_t seed, void* hip_stream);
 
+/* Launch-shape choices of the gradient kernels; 0 in a field keeps the
+ * engine's own choice (made from the LDS footprint, the grid size and the
+ * layer densities; HMC_ROWS_A, HMC_ROWS_B, HMC_THREADS and HMC_DW in the
+ * environment override it when the field is 0). */
+typedef struct {
+    int32_t rows_a;    /* rows per tile of the MLP / branch tower: 0, 16, 32 or 64       */
+    int32_t rows_b;    /* rows per tile of the trunk tower: 0, 16, 32 or 64              */
+    int32_t threads;   /* threads per workgroup of the tile kernels: 0, 256 or 512       */
+    int32_t dw;        /* masked dW: 0 automatic, 1 per-entry sums, 2 dense tile product
+                          (on every layer where the tile height allows it)              */
+} hmc_tuning;
+
+/* hmc_init with explicit launch shapes (tuning NULL: as hmc_init).  A tile
+ * height that does not fit in LDS gives HMC_EUNSUPPORTED; values outside the
+ * listed ones give HMC_EINVAL. */
+hmc_status hmc_init_tuned(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask,
+                          const hmc_data_desc* data, uint64_t seed, void* hip_stream, const hmc_tuning* tuning);
+
+/* Autotuner: builds an engine for every candidate launch shape that fits
+ * (tile heights 16/32/64 for each tower, 256 or 512 threads, per-entry or
+ * dense masked dW where the dense product applies), times one gradient
+ * evaluation of all chains (hmc_time_kernels, reps launches each, HIP
+ * events) and returns the fastest in *best and its milliseconds in *best_ms
+ * (may be NULL).  Uses the current device and its own streams; synchronous;
+ * takes seconds for large networks. */
+hmc_status hmc_autotune(const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                        int32_t reps, hmc_tuning* best, double* best_ms);
+
 /* One iteration of the loop of Algorithm 2 for the listed chains: draw
  * p ~ N(0, M), integrate L leapfrog steps of size eps[i] for chain
  * chain_ids[i] (kick-drift-kick, exactly L gradient evaluations), then

@@ -7,4 +7,5 @@ Algorithm 2 of arXiv 2507.14652).  All compute runs in the HIP library
 arguments to it.
 """
 
-from .binding import Sampler, HMCError, STAT_DTYPE, load, select_mask, sensitivities  # noqa: F401
+from .binding import (HMCError, STAT_DTYPE, Sampler, autotune, autotune_workload, load,  # noqa: F401
+                      select_mask, sensitivities)

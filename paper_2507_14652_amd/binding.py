@@ -26,7 +26,7 @@ ABI_FUNCTIONS = (
     "hmc_init", "hmc_leapfrog", "hmc_sample", "hmc_grad", "hmc_trajectory", "hmc_momentum",
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
     "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
-    "hmc_predict",
+    "hmc_predict", "hmc_init_tuned", "hmc_autotune",
 )
 
 
@@ -57,6 +57,10 @@ class DataDesc(ctypes.Structure):
 class TrajStat(ctypes.Structure):
     _fields_ = [("H0", c_double), ("H1", c_double), ("log_u", c_double),
                 ("accepted", c_int32), ("divergent", c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows_a", c_int32), ("rows_b", c_int32), ("threads", c_int32), ("dw", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -96,6 +100,10 @@ def load():
         "hmc_sensitivity": [POINTER(NetDesc), POINTER(DataDesc), POINTER(c_double), POINTER(c_double), P],
         "hmc_select_mask": [POINTER(c_double), c_int64, c_double, POINTER(c_int64), POINTER(c_int64)],
         "hmc_predict": [P, c_int32, P, c_int64, POINTER(DataDesc), POINTER(c_double), POINTER(c_double)],
+        "hmc_init_tuned": [POINTER(c_void_p), POINTER(NetDesc), POINTER(MaskDesc), POINTER(DataDesc), c_uint64, P,
+                           POINTER(Tuning)],
+        "hmc_autotune": [POINTER(NetDesc), POINTER(MaskDesc), POINTER(DataDesc), c_int32, POINTER(Tuning),
+                         POINTER(c_double)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -171,13 +179,73 @@ def select_mask(s2, tau):
     return idx[:n.value].copy()
 
 
+def _descs(*, kind, widths_a, widths_b, theta0, prior_sd, lik_sd, precision, offs, idx, theta_init=None,
+           inv_mass=None, x=None, y=None, u=None, yq=None, v=None):
+    """The C descriptors of a network, its masks and its data, and the arrays
+    they point into (keep them alive while the descriptors are used)."""
+    wa = np.ascontiguousarray(widths_a, dtype=np.int32)
+    wb = np.ascontiguousarray(widths_b if widths_b is not None else [0], dtype=np.int32)
+    th0 = _f64(theta0)
+    minv = _f64(inv_mass)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    tinit = _f64(theta_init)
+    net = NetDesc(KIND[kind], len(wa), wa.ctypes.data_as(POINTER(c_int32)),
+                  len(wb) if widths_b is not None else 0, wb.ctypes.data_as(POINTER(c_int32)),
+                  _dptr(th0), th0.size, float(prior_sd), float(lik_sd), PRECISION[precision],
+                  _dptr(minv) if minv is not None else None)
+    mask = MaskDesc(len(offs) - 1, offs.ctypes.data_as(POINTER(c_int64)),
+                    idx.ctypes.data_as(POINTER(c_int64)), _dptr(tinit) if tinit is not None else None)
+    keep = [wa, wb, offs, idx, th0, minv, tinit]
+    if kind == "mlp":
+        xa, ya = _f64(x), _f64(y)
+        keep += [xa, ya]
+        data = DataDesc(_dptr(xa), _dptr(ya), xa.shape[0], None, None, None, 0, 0)
+    else:
+        ua, qa, va = _f64(u), _f64(yq), _f64(v)
+        keep += [ua, qa, va]
+        data = DataDesc(None, None, 0, _dptr(ua), _dptr(qa), _dptr(va), ua.shape[0], qa.shape[0])
+    return net, mask, data, keep
+
+
+def _workload_kwargs(w, precision=None):
+    kw = dict(kind=w.kind, widths_a=w.widths_a, widths_b=w.widths_b, theta0=w.theta0,
+              prior_sd=w.prior_sd, lik_sd=w.lik_sd, precision=precision or w.precision,
+              offs=w.offs, idx=w.idx, theta_init=w.theta_init)
+    if w.kind == "mlp":
+        kw.update(x=w.x, y=w.y)
+    else:
+        kw.update(u=w.u, yq=w.yq, v=w.v)
+    return kw
+
+
+def autotune(*, reps=10, **kw):
+    """The fastest launch shape for an engine with these arguments (as for
+    Sampler) and its gradient-evaluation milliseconds (hmc_autotune)."""
+    lib = load()
+    net, mask, data, keep = _descs(**kw)
+    best = Tuning()
+    ms = c_double(0.0)
+    st = lib.hmc_autotune(ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), int(reps), ctypes.byref(best),
+                          ctypes.byref(ms))
+    del keep
+    if st != HMC_OK:
+        raise HMCError(st, lib.hmc_last_error(None).decode())
+    return {k: getattr(best, k) for k, _ in Tuning._fields_}, ms.value
+
+
+def autotune_workload(w, precision=None, reps=10):
+    """autotune() for a ``workloads.Workload``."""
+    return autotune(reps=reps, **_workload_kwargs(w, precision))
+
+
 class Sampler:
     """One engine (hmc_ctx): a network, per-chain masks, data and chain state
     on the current GPU."""
 
     def __init__(self, *, kind, widths_a, widths_b=None, theta0, prior_sd, lik_sd, precision,
                  offs, idx, theta_init=None, inv_mass=None, x=None, y=None, u=None, yq=None, v=None,
-                 seed=0, stream=None):
+                 seed=0, stream=None, tuning=None):
         self._lib = load()
         self._ctx = c_void_p()
         self.kind = kind
@@ -185,32 +253,20 @@ class Sampler:
         self.precision = precision
         self.state_dtype = torch.float64 if precision == "fp64" else torch.float32
         self._np_state = np.float64 if precision == "fp64" else np.float32
-        wa = np.ascontiguousarray(widths_a, dtype=np.int32)
-        wb = np.ascontiguousarray(widths_b if widths_b is not None else [0], dtype=np.int32)
-        th0 = _f64(theta0)
-        minv = _f64(inv_mass)
-        self.offs = np.ascontiguousarray(offs, dtype=np.int64)
-        idx = np.ascontiguousarray(idx, dtype=np.int64)
-        tinit = _f64(theta_init)
-        net = NetDesc(KIND[kind], len(wa), wa.ctypes.data_as(POINTER(c_int32)),
-                      len(wb) if widths_b is not None else 0, wb.ctypes.data_as(POINTER(c_int32)),
-                      _dptr(th0), th0.size, float(prior_sd), float(lik_sd), PRECISION[precision],
-                      _dptr(minv) if minv is not None else None)
-        mask = MaskDesc(len(self.offs) - 1, self.offs.ctypes.data_as(POINTER(c_int64)),
-                        idx.ctypes.data_as(POINTER(c_int64)), _dptr(tinit) if tinit is not None else None)
-        keep = []
-        if kind == "mlp":
-            xa, ya = _f64(x), _f64(y)
-            keep += [xa, ya]
-            data = DataDesc(_dptr(xa), _dptr(ya), xa.shape[0], None, None, None, 0, 0)
-        else:
-            ua, qa, va = _f64(u), _f64(yq), _f64(v)
-            keep += [ua, qa, va]
-            data = DataDesc(None, None, 0, _dptr(ua), _dptr(qa), _dptr(va), ua.shape[0], qa.shape[0])
+        net, mask, data, keep = _descs(kind=kind, widths_a=widths_a, widths_b=widths_b, theta0=theta0,
+                                       prior_sd=prior_sd, lik_sd=lik_sd, precision=precision, offs=offs, idx=idx,
+                                       theta_init=theta_init, inv_mass=inv_mass, x=x, y=y, u=u, yq=yq, v=v)
+        self.offs = keep[2]
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream().cuda_stream
-        st = self._lib.hmc_init(ctypes.byref(self._ctx), ctypes.byref(net), ctypes.byref(mask),
-                                ctypes.byref(data), c_uint64(seed), c_void_p(stream or None))
+        if tuning is None:
+            st = self._lib.hmc_init(ctypes.byref(self._ctx), ctypes.byref(net), ctypes.byref(mask),
+                                    ctypes.byref(data), c_uint64(seed), c_void_p(stream or None))
+        else:
+            tn = Tuning(**{k: int(tuning.get(k, 0)) for k, _ in Tuning._fields_})
+            st = self._lib.hmc_init_tuned(ctypes.byref(self._ctx), ctypes.byref(net), ctypes.byref(mask),
+                                          ctypes.byref(data), c_uint64(seed), c_void_p(stream or None),
+                                          ctypes.byref(tn))
         if st != HMC_OK:
             raise HMCError(st, self._lib.hmc_last_error(None).decode())
         info = Info()
@@ -220,14 +276,9 @@ class Sampler:
         self.n_chains = int(info.n_chains)
 
     @classmethod
-    def from_workload(cls, w, *, seed=0, precision=None, stream=None, inv_mass=None):
-        kw = dict(kind=w.kind, widths_a=w.widths_a, widths_b=w.widths_b, theta0=w.theta0,
-                  prior_sd=w.prior_sd, lik_sd=w.lik_sd, precision=precision or w.precision,
-                  offs=w.offs, idx=w.idx, theta_init=w.theta_init, inv_mass=inv_mass, seed=seed, stream=stream)
-        if w.kind == "mlp":
-            kw.update(x=w.x, y=w.y)
-        else:
-            kw.update(u=w.u, yq=w.yq, v=w.v)
+    def from_workload(cls, w, *, seed=0, precision=None, stream=None, inv_mass=None, tuning=None):
+        kw = _workload_kwargs(w, precision)
+        kw.update(inv_mass=inv_mass, seed=seed, stream=stream, tuning=tuning)
         return cls(**kw)
 
     # ------------------------------------------------------------------

@@ -81,6 +81,7 @@ struct hmc_ctx {
     // resident MLP kernel (weights in LDS, several tiles per workgroup)
     bool resident = false;
     bool force_dense = false;     // sensitivity engines: dense dW (squared terms) on every layer
+    hmc_tuning tune{0, 0, 0, 0};  // launch-shape overrides (0: automatic)
     int kpt = 0, groups = 0, grid_res = 0;
     size_t lds_res = 0;
     GradArgs ga{};
@@ -207,9 +208,10 @@ hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hm
 // Threads per workgroup of a tile kernel.  A workgroup whose LDS leaves room
 // for a second one on the CU runs with 4 waves (two workgroups per CU hide
 // each other's barriers); one that holds the CU's LDS alone runs with 8 waves
-// so that the CU still has 8 waves in flight.  HMC_THREADS (256 or 512)
-// overrides the choice.
-int pick_threads(size_t lds) {
+// so that the CU still has 8 waves in flight.  A tuning value (256 or 512)
+// or else HMC_THREADS overrides the choice.
+int pick_threads(size_t lds, int forced) {
+    if (forced == 256 || forced == 512) return forced;
     if (const char* s = std::getenv("HMC_THREADS")) {
         const int t = std::atoi(s);
         if (t == 256 || t == 512) return t;
@@ -272,11 +274,13 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
 }
 
 // Largest row tile whose LDS footprint fits, shrunk while the grid would
-// leave most compute units idle.  HMC_ROWS_A / HMC_ROWS_B override it.
+// leave most compute units idle.  A tuning value (16, 32 or 64; 0 when it
+// does not fit) or else HMC_ROWS_A / HMC_ROWS_B overrides it.
 // fixed: bytes beside the slabs (staged biases, alignment).
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
-              const char* env) {
+              const char* env, int forced) {
     auto fits = [&](int r) { return tower_lds(w, prec, r) + extra_per_row * r + 64 + 16 + fixed <= g_lds_cap; };
+    if (forced) return fits(forced) ? forced : 0;
     if (const char* s = std::getenv(env)) {
         const int r = std::atoi(s);
         if ((r == 16 || r == 32 || r == 64) && fits(r)) return r;
@@ -379,17 +383,21 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     if (x->kind == HMC_MLP) {
         rows_a = data->n_rows;
         x->Ra = pick_rows(x->A.w, prec, (size_t)x->A.w.back() * 8, bias_bytes(x->A.w, prec, as), rows_a, x->C,
-                          "HMC_ROWS_A");
+                          "HMC_ROWS_A", x->tune.rows_a);
     } else {
         rows_a = data->n_u;
         rows_b = data->n_q;
         nq_pad = roundup((int)rows_b, pad);
         x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, bias_bytes(x->A.w, prec, as), rows_a,
-                          x->C, "HMC_ROWS_A");
-        x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B");
-        if (!x->Rb) return x->fail(HMC_EUNSUPPORTED, "trunk tower does not fit in LDS");
+                          x->C, "HMC_ROWS_A", x->tune.rows_a);
+        x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B", x->tune.rows_b);
+        if (!x->Rb)
+            return x->fail(HMC_EUNSUPPORTED, x->tune.rows_b ? "trunk tower does not fit in LDS at the requested rows per tile"
+                                                            : "trunk tower does not fit in LDS");
     }
-    if (!x->Ra) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS at 16 rows per tile");
+    if (!x->Ra)
+        return x->fail(HMC_EUNSUPPORTED, x->tune.rows_a ? "tower does not fit in LDS at the requested rows per tile"
+                                                        : "tower does not fit in LDS at 16 rows per tile");
     x->tiles_a = (int)((rows_a + x->Ra - 1) / x->Ra);
     x->tiles_b = x->kind == HMC_DEEPONET ? (int)((rows_b + x->Rb - 1) / x->Rb) : 0;
     if ((long long)x->C * x->tiles_a > (1ll << 30) || (long long)x->C * x->tiles_b > (1ll << 30))
@@ -517,13 +525,13 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // The per-kernel limit is set to the device capacity (not this engine's
     // size) so that engines of different shapes in one process coexist.
     HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
-    x->nt_a = pick_threads(x->lds_a);
+    x->nt_a = pick_threads(x->lds_a, x->tune.threads);
     if (x->kind == HMC_DEEPONET) {
         x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
         g.bias_lds_b = (int)x->lds_b;
         x->lds_b += bias_bytes(x->B.w, prec, as);
         HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
-        x->nt_b = pick_threads(x->lds_b);
+        x->nt_b = pick_threads(x->lds_b, x->tune.threads);
     }
 
     // Mask tables: entry codes, per-layer segments, scatter destinations.
@@ -624,8 +632,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     const int nlt = la + lb;
     std::vector<int> bseg((size_t)x->C * std::max(nlt, 1)), dflag((size_t)x->C * std::max(nlt, 1));
     const char* dwenv = std::getenv("HMC_DW");
-    const bool force_dense = dwenv && !std::strcmp(dwenv, "dense");
-    const bool force_gather = dwenv && !std::strcmp(dwenv, "gather");
+    const bool force_dense = x->tune.dw == 2 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "dense"));
+    const bool force_gather = x->tune.dw == 1 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "gather"));
     const int kch = prec == HMC_BF16 ? 32 : 16;
     const int thr = 128;   // BF16: dense when density >= 1/thr
     for (int c = 0; c < x->C; ++c) {
@@ -746,7 +754,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->lds_a32 += bias_bytes(x->A.w, prec, 4);
         e.y_lds = (int)x->lds_a32;
         if (x->kind == HMC_MLP) x->lds_a32 += (size_t)x->Ra32 * x->A.w.back() * 8;
-        x->nt_a32 = pick_threads(x->lds_a32);
+        x->nt_a32 = pick_threads(x->lds_a32, x->tune.threads);
         std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
         fill_tower(w32h, HMC_FP32, g.ta, x->A);
         if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
@@ -777,7 +785,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             x->lds_b32 = energy_lds(g.tb, x->Rb32) + 64;
             e.bias_lds_b = (int)x->lds_b32;
             x->lds_b32 += bias_bytes(x->B.w, prec, 4);
-            x->nt_b32 = pick_threads(x->lds_b32);
+            x->nt_b32 = pick_threads(x->lds_b32, x->tune.threads);
             e.tiles_b = x->tiles_b32;
             e.xb = upload32(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);
             const int pp = g.ta.wp[la];
@@ -913,7 +921,7 @@ extern "C" {
 namespace {
 
 hmc_status init_ctx(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
-                    uint64_t seed, void* hip_stream, bool sens) {
+                    uint64_t seed, void* hip_stream, bool sens, const hmc_tuning* tune = nullptr) {
     if (!out) { g_init_error = "out is NULL"; return HMC_EINVAL; }
     *out = nullptr;
     std::string err;
@@ -922,6 +930,7 @@ hmc_status init_ctx(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
     hmc_ctx* x = new (std::nothrow) hmc_ctx();
     if (!x) { g_init_error = "out of host memory"; return HMC_ENOMEM; }
     x->force_dense = sens;
+    if (tune) x->tune = *tune;
     x->kind = net->kind;
     x->prec = net->precision;
     x->A.w.assign(net->widths_a, net->widths_a + net->n_widths_a);
@@ -972,6 +981,75 @@ hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
                     uint64_t seed, void* hip_stream) {
     g_init_error.clear();
     return init_ctx(out, net, mask, data, seed, hip_stream, false);
+}
+
+namespace {
+hmc_status check_tuning(const hmc_tuning* t) {
+    auto rows_ok = [](int r) { return r == 0 || r == 16 || r == 32 || r == 64; };
+    if (!rows_ok(t->rows_a) || !rows_ok(t->rows_b)) { g_init_error = "tuning rows must be 0, 16, 32 or 64"; return HMC_EINVAL; }
+    if (t->threads != 0 && t->threads != 256 && t->threads != 512) {
+        g_init_error = "tuning threads must be 0, 256 or 512";
+        return HMC_EINVAL;
+    }
+    if (t->dw < 0 || t->dw > 2) { g_init_error = "tuning dw must be 0, 1 or 2"; return HMC_EINVAL; }
+    return HMC_OK;
+}
+}  // namespace
+
+hmc_status hmc_init_tuned(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask,
+                          const hmc_data_desc* data, uint64_t seed, void* hip_stream, const hmc_tuning* tuning) {
+    g_init_error.clear();
+    if (tuning) {
+        const hmc_status st = check_tuning(tuning);
+        if (st != HMC_OK) return st;
+    }
+    return init_ctx(out, net, mask, data, seed, hip_stream, false, tuning);
+}
+
+hmc_status hmc_autotune(const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
+                        int32_t reps, hmc_tuning* best, double* best_ms) {
+    g_init_error.clear();
+    if (!best || reps < 1) { g_init_error = "best must not be NULL and reps >= 1"; return HMC_EINVAL; }
+    {
+        std::string err;
+        const hmc_status st = validate(net, mask, data, err);
+        if (st != HMC_OK) { g_init_error = err; return st; }
+    }
+    const bool deep = net->kind == HMC_DEEPONET;
+    std::vector<int> ra = {16, 32, 64}, rb = deep ? std::vector<int>{16, 32, 64} : std::vector<int>{0};
+    double bt = -1.0;
+    hmc_tuning bb{0, 0, 0, 0};
+    std::string last;
+    for (int a : ra)
+        for (int b : rb)
+            for (int th : {256, 512})
+                for (int dw : {1, 2}) {
+                    const hmc_tuning t{a, b, th, dw};
+                    hmc_ctx* x = nullptr;
+                    if (init_ctx(&x, net, mask, data, 0, nullptr, false, &t) != HMC_OK) {
+                        last = g_init_error;   // e.g. a tile that does not fit in LDS
+                        continue;
+                    }
+                    // candidates whose dense request changed nothing repeat the per-entry one
+                    if (dw == 2 && x->dense_layers == 0) { hmc_destroy(x); continue; }
+                    double ms[4] = {0, 0, 0, 0};
+                    const hmc_status st = hmc_time_kernels(x, reps, ms);
+                    if (st != HMC_OK) {
+                        g_init_error = x->err;
+                        hmc_destroy(x);
+                        return st;
+                    }
+                    const double tot = ms[0] + ms[1] + ms[2] + ms[3];
+                    if (bt < 0.0 || tot < bt) { bt = tot; bb = t; }
+                    hmc_destroy(x);
+                }
+    if (bt < 0.0) {
+        g_init_error = "no candidate launch shape fits: " + last;
+        return HMC_EUNSUPPORTED;
+    }
+    *best = bb;
+    if (best_ms) *best_ms = bt;
+    return HMC_OK;
 }
 
 hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma, double* s2,

@@ -9,6 +9,8 @@ import re
 import numpy as np
 import pytest
 
+import workloads
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "hmc.h")
 
@@ -145,3 +147,35 @@ def test_sensitivity_rejects_bad_input_on_the_host():
     assert call(sigma=np.full(13, np.inf)) == B.HMC_EINVAL
     assert call(kind=4) == B.HMC_EINVAL
     assert "kind" in lib.hmc_last_error(None).decode()
+
+
+@needs_lib
+@pytest.mark.parametrize("tune,needle", [
+    ((7, 0, 0, 0), "rows"), ((16, 8, 0, 0), "rows"), ((16, 0, 128, 0), "threads"), ((16, 0, 256, 3), "dw"),
+])
+def test_tuned_init_rejects_bad_launch_shapes(tune, needle):
+    """A tuning record outside the allowed shapes is refused before the
+    engine is built."""
+    lib = binding.load()
+    w = workloads.make("regress2d_fp32", n_rows=20, n_chains=1)
+    net, mask, data, keep = binding._descs(**binding._workload_kwargs(w))
+    ctx = ctypes.c_void_p()
+    t = binding.Tuning(*tune)
+    st = lib.hmc_init_tuned(ctypes.byref(ctx), ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), 0, None,
+                            ctypes.byref(t))
+    assert st == binding.HMC_EINVAL and not ctx.value
+    assert needle in lib.hmc_last_error(None).decode()
+
+
+@needs_lib
+def test_autotune_rejects_bad_arguments_on_the_host():
+    lib = binding.load()
+    w = workloads.make("regress2d_fp32", n_rows=20, n_chains=1)
+    net, mask, data, keep = binding._descs(**binding._workload_kwargs(w))
+    best = binding.Tuning()
+    assert lib.hmc_autotune(ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), 0, ctypes.byref(best),
+                            None) == binding.HMC_EINVAL
+    net.lik_sd = -1.0
+    assert lib.hmc_autotune(ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), 3, ctypes.byref(best),
+                            None) == binding.HMC_EINVAL
+    assert "lik_sd" in lib.hmc_last_error(None).decode()
