@@ -15,6 +15,7 @@ timed region); --config selects another named workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -27,9 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {  # MI355X dense peaks
-    "f64": 78.6, "f32": 157.3, "bf16": 2500.0,
+    "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0,
 }
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
 
 
 def algorithmic_flops(w, part=None):
@@ -456,6 +457,10 @@ def main():
     ap.add_argument("--timing-reps", type=int, default=50)
     ap.add_argument("--adapt", type=int, default=150,
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
+    ap.add_argument("--precision", choices=("fp64", "fp32", "bf16", "bf16x3"),
+                    help="run --config's workload at another precision (a comparison, not the headline line)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shapes with the library's autotuner (untimed) instead of its heuristic")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
     ap.add_argument("--predict", action="store_true",
@@ -487,11 +492,14 @@ def main():
     import torch
 
     import workloads
-    from paper_2507_14652_amd import Sampler
+    from paper_2507_14652_amd import Sampler, autotune_workload
     from paper_2507_14652_amd.warmup import adapt_step_size
 
     w = workloads.make(args.config)
-    s = Sampler.from_workload(w, seed=2507)
+    if args.precision:
+        w = dataclasses.replace(w, precision=args.precision)
+    tuning = autotune_workload(w, reps=10)[0] if args.autotune else None
+    s = Sampler.from_workload(w, seed=2507, tuning=tuning)
     C, L = w.n_chains, w.L
     st_dtype = torch.float64 if w.precision == "fp64" else torch.float32
     out = torch.empty((args.steps, w.nnz), dtype=st_dtype, device="cuda")
@@ -540,7 +548,10 @@ def main():
                    "rows": w.n_rows(), "chains": C, "selected_per_chain": int(w.nnz // C), "L": L,
                    "eps_start": w.eps, "eps_adapt_iters": args.adapt,
                    "eps_median": float(np.median(eps_c)), "eps_min": float(np.min(eps_c)),
-                   "eps_max": float(np.max(eps_c))},
+                   "eps_max": float(np.max(eps_c)),
+                   "launch": {"autotuned": bool(args.autotune), "dw": (tuning or {}).get("dw", 0),
+                              **{k: s.info[k] for k in ("rows_per_tile_a", "rows_per_tile_b", "threads_a",
+                                                        "threads_b")}}},
         "acceptance": acc,
         "kernel_ms": {"grad_main": ms[0], "trunk_fwd": ms[1], "trunk_bwd": ms[2], "reduce": ms[3]},
         "roofline": roof,

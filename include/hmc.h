@@ -28,7 +28,7 @@
  *  - Arrays documented "host or device" may be host memory or device memory
  *    of the engine's GPU; the library copies with the unified-address copy.
  *  - The "state type" of an engine is double for HMC_FP64 and float for
- *    HMC_FP32 and HMC_BF16; positions, momenta and gradients cross the ABI in
+ *    HMC_FP32, HMC_BF16 and HMC_BF16X3; positions, momenta and gradients cross the ABI in
  *    that type, in the CSR order of the mask (chain by chain).
  *  - Work is queued on the engine's stream.  Functions that return host
  *    results (stats, energies, copies to host) synchronise that stream.
@@ -61,8 +61,13 @@ typedef enum {
 /* Number format of the layer products.  FP64: everything in double.
  * FP32: products and states in float, energies in double.  BF16: products
  * take bfloat16 operands with float accumulation, states in float, energies
- * in double. */
-typedef enum { HMC_FP64 = 0, HMC_FP32 = 1, HMC_BF16 = 2 } hmc_precision;
+ * in double.  BF16X3: operands stay in float and each product is the sum of
+ * three bfloat16 products of their high and low bfloat16 parts (about 16
+ * significant bits per product, float accumulation), for BF16 matrix-core
+ * throughput with trajectories close to FP32 ones; states in float,
+ * energies in double.  The energies of the Metropolis test of BF16 and
+ * BF16X3 engines come from a float forward pass. */
+typedef enum { HMC_FP64 = 0, HMC_FP32 = 1, HMC_BF16 = 2, HMC_BF16X3 = 3 } hmc_precision;
 
 /* Network family (Sec. 2 and App. A).  An MLP is one fully connected tower;
  * a DeepONet has a branch tower over input-function samples and a trunk

@@ -19,7 +19,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmc.so")
 
 HMC_OK, HMC_EINVAL, HMC_ENOMEM, HMC_EDEVICE, HMC_ESTATE, HMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 KIND = {"mlp": 0, "deeponet": 1}
 
 ABI_FUNCTIONS = (

@@ -21,9 +21,11 @@ thread_local std::string g_init_error;
 
 size_t g_lds_cap = 160 * 1024;   // LDS per workgroup on gfx950; replaced by the device's value
 
-int pad_of(int prec) { return prec == HMC_BF16 ? 32 : 16; }
+// K chunk of the product (bf16 MFMAs take 32), LDS row padding in elements,
+// and the stored product type (split BF16 keeps float operands).
+int pad_of(int prec) { return prec == HMC_BF16 || prec == HMC_BF16X3 ? 32 : 16; }
 int lpad_of(int prec) { return prec == HMC_BF16 ? 8 : 4; }
-size_t tsize_of(int prec) { return prec == HMC_FP64 ? 8 : prec == HMC_FP32 ? 4 : 2; }   // product type
+size_t tsize_of(int prec) { return prec == HMC_FP64 ? 8 : prec == HMC_BF16 ? 2 : 4; }
 size_t asize_of(int prec) { return prec == HMC_FP64 ? 8 : 4; }                          // accumulator / bias type
 size_t ssize_of(int prec) { return prec == HMC_FP64 ? 8 : 4; }                          // state type
 int roundup(int x, int m) { return (x + m - 1) / m * m; }
@@ -37,13 +39,33 @@ uint16_t to_bf16_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Stores v in the product type at index i of a byte buffer.
+// BF16 bits of f (round to nearest even) and their value as a float.
+uint16_t bf16_round(float f, float* back) {
+    const uint16_t b = to_bf16_bits(f);
+    const uint32_t u = (uint32_t)b << 16;
+    std::memcpy(back, &u, 4);
+    return b;
+}
+
+// Stores v in the product type at index i of a byte buffer.  Split BF16
+// (buffers whose rows are multiples of eight elements): element i is the
+// pair hi = bf16(v), lo = bf16(v - hi) at BF16 slots (i / 8) * 16 + i % 8
+// and 8 slots on, as the kernels read it.
 void put_t(std::vector<unsigned char>& buf, int prec, size_t i, double v) {
     if (prec == HMC_FP64) { std::memcpy(&buf[i * 8], &v, 8); return; }
     const float f = (float)v;
     if (prec == HMC_FP32) { std::memcpy(&buf[i * 4], &f, 4); return; }
-    const uint16_t b = to_bf16_bits(f);
-    std::memcpy(&buf[i * 2], &b, 2);
+    if (prec == HMC_BF16) {
+        const uint16_t b = to_bf16_bits(f);
+        std::memcpy(&buf[i * 2], &b, 2);
+        return;
+    }
+    float hf;
+    const uint16_t hi = bf16_round(f, &hf);
+    const uint16_t lo = to_bf16_bits(f - hf);
+    const size_t slot = (i >> 3) * 16 + (i & 7);
+    std::memcpy(&buf[slot * 2], &hi, 2);
+    std::memcpy(&buf[(slot + 8) * 2], &lo, 2);
 }
 void put_a(std::vector<unsigned char>& buf, int prec, size_t i, double v) {
     if (prec == HMC_FP64) { std::memcpy(&buf[i * 8], &v, 8); return; }
@@ -86,7 +108,7 @@ struct hmc_ctx {
     size_t lds_res = 0;
     GradArgs ga{};
     StateArgs sa{};
-    // BF16 engines: FP32 energy pass over an FP32 shadow of the weights
+    // BF16 and split-BF16 engines: FP32 energy pass over an FP32 shadow of the weights
     bool energy32 = false;
     GradArgs ga32{};
     int Ra32 = 0, Rb32 = 0, tiles_a32 = 0, tiles_b32 = 0, grid_a32 = 0, grid_b32 = 0;
@@ -151,7 +173,7 @@ hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hm
                     std::string& err) {
     if (!net || !mask || !data) { err = "net, mask and data must be non-NULL"; return HMC_EINVAL; }
     if (net->kind != HMC_MLP && net->kind != HMC_DEEPONET) { err = "unknown network kind"; return HMC_EINVAL; }
-    if (net->precision < HMC_FP64 || net->precision > HMC_BF16) { err = "unknown precision"; return HMC_EINVAL; }
+    if (net->precision < HMC_FP64 || net->precision > HMC_BF16X3) { err = "unknown precision"; return HMC_EINVAL; }
     HMC_TRY(check_tower(net->widths_a, net->n_widths_a, "widths_a", err));
     std::vector<int> wa(net->widths_a, net->widths_a + net->n_widths_a), wb;
     long long P = tower_count(wa);
@@ -308,7 +330,7 @@ hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
 
 int update_grid(const hmc_ctx* x) { return (x->max_n + 255) / 256; }
 
-// FP32 energy pass of BF16 engines: the likelihood partials that define U in
+// FP32 energy pass of BF16 and split-BF16 engines: the likelihood partials that define U in
 // the Hamiltonian, at the current positions.
 hmc_status launch_energy(hmc_ctx* x, hipStream_t s) {
     if (!x->energy32) return HMC_OK;
@@ -585,7 +607,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // FP32 MLP workload it is slower than one tile per workgroup (the tiles of
     // a workgroup run one after another at one workgroup per compute unit), so
     // it is opt-in.
-    if (x->kind == HMC_MLP && !x->force_dense && x->max_n <= 8 * HMC_NT && std::getenv("HMC_RESIDENT") &&
+    if (x->kind == HMC_MLP && !x->force_dense && prec != HMC_BF16X3 && x->max_n <= 8 * HMC_NT &&
+        std::getenv("HMC_RESIDENT") &&
         !std::strcmp(std::getenv("HMC_RESIDENT"), "1")) {
         const int E = (int)(16 / ts);
         long long wl = 0;
@@ -634,7 +657,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     const char* dwenv = std::getenv("HMC_DW");
     const bool force_dense = x->tune.dw == 2 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "dense"));
     const bool force_gather = x->tune.dw == 1 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "gather"));
-    const int kch = prec == HMC_BF16 ? 32 : 16;
+    const int kch = pad_of(prec);
     const int thr = 128;   // BF16: dense when density >= 1/thr
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
@@ -648,7 +671,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             const long long nw = b - seg[(size_t)c * nseg + L];
             const int R = L < la ? x->Ra : x->Rb;
             const bool can = nw > 0 && R % kch == 0;
-            const bool autod = prec == HMC_BF16 && tp.w[l] >= 64 && tp.w[l + 1] >= 64 &&
+            const bool autod = (prec == HMC_BF16 || prec == HMC_BF16X3) && tp.w[l] >= 64 && tp.w[l + 1] >= 64 &&
                                nw * thr >= (long long)tp.w[l] * tp.w[l + 1];
             const bool dense = can && !force_gather && (force_dense || autod || x->force_dense);
             dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
@@ -734,11 +757,12 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * (x->resident ? x->groups : x->tiles_a));
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
 
-    // BF16 engines: FP32 shadow for the energy pass (same offsets as wbuf).
+    // BF16 and split-BF16 engines: FP32 shadow for the energy pass (same
+    // offsets as wbuf).
     // Built after every field of the BF16 arguments is final, since the
     // energy arguments start as a copy of them.
     void* w32 = nullptr;
-    if (prec == HMC_BF16) {
+    if (prec == HMC_BF16 || prec == HMC_BF16X3) {
         x->energy32 = true;
         GradArgs& e = x->ga32;
         e = g;
@@ -755,14 +779,17 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         e.y_lds = (int)x->lds_a32;
         if (x->kind == HMC_MLP) x->lds_a32 += (size_t)x->Ra32 * x->A.w.back() * 8;
         x->nt_a32 = pick_threads(x->lds_a32, x->tune.threads);
-        std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
-        fill_tower(w32h, HMC_FP32, g.ta, x->A);
-        if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
-        w32 = x->dalloc((size_t)x->C * g.wstride * 4);
-        if (!w32) return x->fail(HMC_ENOMEM, "device allocation of the FP32 weight shadow failed");
-        for (int c = 0; c < x->C; ++c)
-            HMC_HIP(x, hipMemcpy((char*)w32 + (size_t)c * g.wstride * 4, w32h.data(), w32h.size(), hipMemcpyHostToDevice));
-        e.wbuf = w32;
+        {
+            std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
+            fill_tower(w32h, HMC_FP32, g.ta, x->A);
+            if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
+            w32 = x->dalloc((size_t)x->C * g.wstride * 4);
+            if (!w32) return x->fail(HMC_ENOMEM, "device allocation of the FP32 weight shadow failed");
+            for (int c = 0; c < x->C; ++c)
+                HMC_HIP(x, hipMemcpy((char*)w32 + (size_t)c * g.wstride * 4, w32h.data(), w32h.size(),
+                                     hipMemcpyHostToDevice));
+            e.wbuf = w32;
+        }
         auto upload32 = [&](const double* src, long long rows, int w, int wp, int R, int tiles) -> void* {
             std::vector<unsigned char> h((size_t)tiles * R * wp * 4, 0);
             for (long long r = 0; r < rows; ++r)
@@ -1065,7 +1092,7 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
     std::vector<int64_t> offs = {0, P}, idx((size_t)P);
     for (int64_t k = 0; k < P; ++k) idx[(size_t)k] = k;
     hmc_net_desc n2 = *net;
-    if (n2.precision == HMC_BF16) n2.precision = HMC_FP32;
+    if (n2.precision == HMC_BF16 || n2.precision == HMC_BF16X3) n2.precision = HMC_FP32;
     n2.inv_mass_diag = nullptr;
     hmc_mask_desc m{1, offs.data(), idx.data(), nullptr};
     // targets are not used; the engine keeps a zero array in their place
@@ -1157,7 +1184,7 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
                  inputs->n_q > (1ll << 24)))
         return x->fail(HMC_EINVAL, "DeepONet inputs need u, yq and 1 <= n_u, n_q <= 2^24");
     if (!mean) return x->fail(HMC_EINVAL, "mean must not be NULL");
-    // BF16 engines predict through their FP32 weight shadow
+    // BF16 and split-BF16 engines predict through the FP32 energy-pass plan
     const bool f32 = x->energy32;
     const int P = f32 ? (int)HMC_FP32 : x->prec;
     GradArgs g = f32 ? x->ga32 : x->ga;

@@ -12,11 +12,17 @@
 // the drift and the scatter of the new positions into the dense weights.
 //
 // Product tiles use the 16x16 MFMA shapes of CDNA4: f64 16x16x4, f32 16x16x4
-// and bf16 16x16x32 (f32 accumulation).  Each lane supplies row (lane % 16)
+// and bf16 16x16x32 (f32 accumulation).  The split-BF16 precision stores
+// each operand as the sum of two BF16 values and takes three bf16 MFMAs per
+// product (see mma1 below).  Each lane supplies row (lane % 16)
 // of the A operand and column (lane % 16) of the B operand with K-slots
 // picked by lane / 16; it receives four accumulator rows of column lane % 16:
 // rows 4 * (lane / 16) + v for f32 and bf16, rows lane / 16 + 4 v for f64
 // (measured on gfx950; the f64 A rows are permuted to match the f32 layout).
+// Split-BF16 operands are stored pre-split: each group of eight consecutive
+// elements of a row takes 32 bytes, the eight high BF16 parts and then the
+// eight low ones, so one 32-byte access gives a lane both halves of its
+// fragment and the products need no conversion.
 // Any K permutation that both
 // operands share leaves the product unchanged, so a lane loads VEC
 // consecutive K values per 16-byte (or 32-byte) access and feeds them to
@@ -31,6 +37,11 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b16v __attribute__((ext_vector_type(16), aligned(16)));
+
+// Storage unit of one split-BF16 element (4 bytes).  Opaque on purpose:
+// elements are read and written only through ld1/st1/ld4/st4 below.
+struct sb3 { uint32_t bits; };
 
 namespace {
 
@@ -52,6 +63,73 @@ template <> struct PT<2> {
     typedef f4v Acc;   typedef b8v Frag;  typedef b4v O4;
     static constexpr int KCH = 32, VEC = 8;
 };
+// Split BF16: pre-split storage (sb3), K chunks of the bf16 MFMA; a
+// fragment is the 32-byte group of eight elements, high parts then low.
+template <> struct PT<3> {
+    typedef sb3 T;     typedef float A;   typedef float S;
+    typedef f4v Acc;   typedef b16v Frag; typedef f4v O4;
+    static constexpr int KCH = 32, VEC = 8;
+};
+
+// Element access in the stored product type.  row: the start of a row
+// (16-byte aligned); k: the element's index in the row.  Split BF16 keeps
+// element k at BF16 slot (k / 8) * 16 + k % 8 (high part) and 8 slots on
+// (low part); the split is hi = bf16(v), lo = bf16(v - hi), both rounded to
+// nearest even.  A buffer whose row length is a multiple of eight may also
+// be addressed with flat indices from its start.
+template <int P>
+__device__ __forceinline__ typename PT<P>::A ld1(const typename PT<P>::T* row, long long k) {
+    if constexpr (P == 3) {
+        const __bf16* b = reinterpret_cast<const __bf16*>(row) + (k >> 3) * 16 + (k & 7);
+        return (float)b[0] + (float)b[8];
+    } else {
+        return (typename PT<P>::A)row[k];
+    }
+}
+template <int P>
+__device__ __forceinline__ void st1(typename PT<P>::T* row, long long k, typename PT<P>::A v) {
+    if constexpr (P == 3) {
+        __bf16* b = reinterpret_cast<__bf16*>(row) + (k >> 3) * 16 + (k & 7);
+        const __bf16 h = (__bf16)v;
+        b[0] = h;
+        b[8] = (__bf16)(v - (float)h);
+    } else {
+        row[k] = (typename PT<P>::T)v;
+    }
+}
+// Four consecutive elements n0 .. n0 + 3 (n0 a multiple of 4).
+template <int P>
+__device__ __forceinline__ void st4(typename PT<P>::T* row, int n0, const typename PT<P>::A (&v)[4]) {
+    if constexpr (P == 3) {
+        b4v h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            h[e] = (__bf16)v[e];
+            l[e] = (__bf16)(v[e] - (float)h[e]);
+        }
+        __bf16* b = reinterpret_cast<__bf16*>(row) + (n0 >> 3) * 16 + (n0 & 7);
+        *reinterpret_cast<b4v*>(b) = h;
+        *reinterpret_cast<b4v*>(b + 8) = l;
+    } else {
+        typename PT<P>::O4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = (typename PT<P>::T)v[e];
+        *reinterpret_cast<typename PT<P>::O4*>(row + n0) = o;
+    }
+}
+template <int P>
+__device__ __forceinline__ void ld4(const typename PT<P>::T* row, int n0, typename PT<P>::A (&v)[4]) {
+    if constexpr (P == 3) {
+        const __bf16* b = reinterpret_cast<const __bf16*>(row) + (n0 >> 3) * 16 + (n0 & 7);
+        const b4v h = *reinterpret_cast<const b4v*>(b), l = *reinterpret_cast<const b4v*>(b + 8);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (float)h[e] + (float)l[e];
+    } else {
+        const typename PT<P>::O4 o = *reinterpret_cast<const typename PT<P>::O4*>(row + n0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (typename PT<P>::A)o[e];
+    }
+}
 
 __device__ __forceinline__ void mma(d4v& c, const d4v& a, const d4v& b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
@@ -72,7 +150,7 @@ __device__ __forceinline__ void mma(f4v& c, const b8v& a, const b8v& b) {
 // One MFMA of a chunk: element e of the lane's K values (FP64 and FP32 take
 // four 16x16x4 MFMAs per 16-wide chunk, BF16 one 16x16x32).  NE<P> is the
 // number of MFMAs per chunk.
-template <int P> constexpr int NE = (P == 2) ? 1 : 4;
+template <int P> constexpr int NE = (P >= 2) ? 1 : 4;
 __device__ __forceinline__ void mma1(d4v& c, const d4v& a, const d4v& b, int e) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], c, 0, 0, 0);
 }
@@ -81,6 +159,22 @@ __device__ __forceinline__ void mma1(f4v& c, const f4v& a, const f4v& b, int e) 
 }
 __device__ __forceinline__ void mma1(f4v& c, const b8v& a, const b8v& b, int) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// Split BF16 (the "bf16x3" scheme of mixed-precision GEMM emulation): each
+// operand x is stored as hi + lo with hi = bf16(x) and lo = bf16(x - hi)
+// (unit roundoff 2^-8, so |x - hi - lo| <= 2^-16 |x|); the product sums
+// hi*hi + hi*lo + lo*hi in FP32.  The dropped lo*lo term is at most 2^-16 of
+// |a b|, so each product carries about 16 significant bits against 8 for a
+// single BF16 product.  A fragment holds the eight high parts in elements
+// 0..7 and the low parts in 8..15.
+__device__ __forceinline__ void mma1(f4v& c, const b16v& a, const b16v& b, int) {
+    const b8v ah = __builtin_shufflevector(a, a, 0, 1, 2, 3, 4, 5, 6, 7);
+    const b8v al = __builtin_shufflevector(a, a, 8, 9, 10, 11, 12, 13, 14, 15);
+    const b8v bh = __builtin_shufflevector(b, b, 0, 1, 2, 3, 4, 5, 6, 7);
+    const b8v bl = __builtin_shufflevector(b, b, 8, 9, 10, 11, 12, 13, 14, 15);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ double act_tanh(double x) { return tanh(x); }
@@ -323,25 +417,25 @@ template <int P> struct EpiTanh {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const A* bias; T* out; int ld;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
-        typename PT<P>::O4 o;
+        A o[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            if constexpr (P == 2) o[v] = (T)tanh_bf16(acc[v] + bias[n0 + v]);
-            else o[v] = (T)act_tanh((A)acc[v] + bias[n0 + v]);
+            if constexpr (P == 2) o[v] = tanh_bf16(acc[v] + bias[n0 + v]);
+            else o[v] = act_tanh((A)acc[v] + bias[n0 + v]);
         }
-        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+        st4<P>(out + r * ld, n0, o);
     }
 };
 
 // Plain store (adjoints of linear outputs).
 template <int P> struct EpiStore {
-    typedef typename PT<P>::T T;
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     T* out; int ld;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
-        typename PT<P>::O4 o;
+        A o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[v] = (T)acc[v];
-        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+        for (int v = 0; v < 4; ++v) o[v] = (A)acc[v];
+        st4<P>(out + r * ld, n0, o);
     }
 };
 
@@ -350,15 +444,11 @@ template <int P> struct EpiBack {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     T* io; int ld;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
-        typename PT<P>::O4* p = reinterpret_cast<typename PT<P>::O4*>(io + r * ld + n0);
-        const typename PT<P>::O4 a = *p;
-        typename PT<P>::O4 o;
+        A av[4], o[4];
+        ld4<P>(io + r * ld, n0, av);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const A av = (A)a[v];
-            o[v] = (T)((A)acc[v] * ((A)1 - av * av));
-        }
-        *p = o;
+        for (int v = 0; v < 4; ++v) o[v] = (A)acc[v] * ((A)1 - av[v] * av[v]);
+        st4<P>(io + r * ld, n0, o);
     }
 };
 
@@ -372,20 +462,20 @@ template <int P> struct EpiMlpHead {
     const double* y; int d_out; int row0; int nrows; double iv;
     double sq;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) {
-        typename PT<P>::O4 o;
+        A o[4];
         const int row = row0 + r;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int n = n0 + v;
-            T d = (T)0;
+            A d = (A)0;
             if (n < d_out && row < nrows) {
                 const double res = ((double)acc[v] + (double)bias[n]) - y[r * d_out + n];
                 sq += res * res;
-                d = (T)(A)(res * iv);
+                d = (A)(res * iv);
             }
             o[v] = d;
         }
-        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+        st4<P>(out + r * ld, n0, o);
     }
 };
 
@@ -421,14 +511,14 @@ template <int P> struct EpiBranchOut {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const A* bias; T* out; int ld; T* bt; int bt_ld; int col0; int nvalid; bool store;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
-        typename PT<P>::O4 o;
+        A o[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const T tv = (T)((A)acc[v] + bias[n0 + v]);
+            const A tv = (A)acc[v] + bias[n0 + v];
             o[v] = tv;
-            if (store) bt[(size_t)(n0 + v) * bt_ld + col0 + r] = (r < nvalid) ? tv : (T)0;
+            if (store) st1<P>(bt + (size_t)(n0 + v) * bt_ld, col0 + r, (r < nvalid) ? tv : (A)0);
         }
-        *reinterpret_cast<typename PT<P>::O4*>(out + r * ld + n0) = o;
+        st4<P>(out + r * ld, n0, o);
     }
 };
 
@@ -438,15 +528,15 @@ template <int P> struct EpiTrunkOut {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const A* bias; T* tm; int tm_ld; T* tt; int tt_ld; int row0; int nvalid;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
-        typename PT<P>::O4 o;
+        A o[4];
         const bool ok = r < nvalid;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const T tv = ok ? (T)((A)acc[v] + bias[n0 + v]) : (T)0;
+            const A tv = ok ? (A)acc[v] + bias[n0 + v] : (A)0;
             o[v] = tv;
-            tt[(size_t)(n0 + v) * tt_ld + row0 + r] = tv;
+            st1<P>(tt + (size_t)(n0 + v) * tt_ld, row0 + r, tv);
         }
-        *reinterpret_cast<typename PT<P>::O4*>(tm + (size_t)(row0 + r) * tm_ld + n0) = o;
+        st4<P>(tm + (size_t)(row0 + r) * tm_ld, n0, o);
     }
 };
 
@@ -460,22 +550,22 @@ template <int P> struct EpiCombine {
     const double* v; int nq; int nvalid; int row0; double b0; double iv; bool store;
     double sq; double sdg;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) {
-        typename PT<P>::O4 o;
+        A o[4];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const int q = n0 + w;
-            T d = (T)0;
+            A d = (A)0;
             if (q < nq && r < nvalid) {
                 const double res = ((double)acc[w] + b0) - v[(size_t)(row0 + r) * nq + q];
                 sq += res * res;
                 const double dd = res * iv;
                 sdg += dd;
-                d = (T)(A)dd;
+                d = (A)dd;
             }
             o[w] = d;
-            if (store) dgt[(size_t)q * dgt_ld + col0 + r] = d;
+            if (store) st1<P>(dgt + (size_t)q * dgt_ld, col0 + r, d);
         }
-        if (store) *reinterpret_cast<typename PT<P>::O4*>(dg + r * dg_ld + n0) = o;
+        if (store) st4<P>(dg + r * dg_ld, n0, o);
     }
 };
 
@@ -492,6 +582,20 @@ template <int P> struct EpiCombine {
 template <bool SQ, class V> __device__ __forceinline__ V sq_if(V v) {
     if constexpr (SQ) return v * v;
     else return v;
+}
+
+// K slot e of a fragment from element k of a row (the dense weight-gradient
+// operands are read one element per tile row).
+template <int P, bool SQ>
+__device__ __forceinline__ void frag_put(typename PT<P>::Frag& f, int e, const typename PT<P>::T* row, int k) {
+    if constexpr (P == 3) {
+        static_assert(!SQ, "squared terms are formed in FP32 and FP64 only");
+        const __bf16* b = reinterpret_cast<const __bf16*>(row) + (k >> 3) * 16 + (k & 7);
+        f[e] = b[0];
+        f[e + 8] = b[8];
+    } else {
+        f[e] = sq_if<SQ>(row[k]);
+    }
 }
 
 template <int P, int R, bool SQ = false>
@@ -512,10 +616,11 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
             A s = (A)0;
             if (j == 0xFFFF) {
 #pragma unroll 8
-                for (int r = 0; r < R; ++r) s += sq_if<SQ>((A)D[r * ld + i]);
+                for (int r = 0; r < R; ++r) s += sq_if<SQ>(ld1<P>(D + r * ld, i));
             } else {
 #pragma unroll 8
-                for (int r = 0; r < R; ++r) s = fma(sq_if<SQ>((A)D[r * ld + i]), sq_if<SQ>((A)X[r * lx + j]), s);
+                for (int r = 0; r < R; ++r)
+                    s = fma(sq_if<SQ>(ld1<P>(D + r * ld, i)), sq_if<SQ>(ld1<P>(X + r * lx, j)), s);
             }
             part[k] = s;
         }
@@ -529,9 +634,10 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
         const int cd = code[k0 + e];
         const int i = cd >> 16, j = cd & 0xFFFF;
         if (j == 0xFFFF) {
-            for (int r = sub; r < R; r += lpe) s += sq_if<SQ>((A)D[r * ld + i]);
+            for (int r = sub; r < R; r += lpe) s += sq_if<SQ>(ld1<P>(D + r * ld, i));
         } else {
-            for (int r = sub; r < R; r += lpe) s = fma(sq_if<SQ>((A)D[r * ld + i]), sq_if<SQ>((A)X[r * lx + j]), s);
+            for (int r = sub; r < R; r += lpe)
+                s = fma(sq_if<SQ>(ld1<P>(D + r * ld, i)), sq_if<SQ>(ld1<P>(X + r * lx, j)), s);
         }
     }
     for (int o = 1; o < lpe; o <<= 1) s += __shfl_xor(s, o, 64);
@@ -605,9 +711,9 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
 #pragma unroll
-                for (int bi = 0; bi < BI; ++bi) a[bi][e] = sq_if<SQ>(D[(r0 + e) * ld + ic[bi]]);
+                for (int bi = 0; bi < BI; ++bi) frag_put<P, SQ>(a[bi], e, D + (r0 + e) * ld, ic[bi]);
 #pragma unroll
-                for (int bj = 0; bj < BJ; ++bj) b[bj][e] = sq_if<SQ>(X[(r0 + e) * lx + jc[bj]]);
+                for (int bj = 0; bj < BJ; ++bj) frag_put<P, SQ>(b[bj], e, X + (r0 + e) * lx, jc[bj]);
             }
 #pragma unroll
             for (int e = 0; e < NE<P>; ++e)
@@ -638,7 +744,7 @@ __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, con
     // 4 x 2 for more operand reuse
     if constexpr (R % PT<P>::KCH == 0) {
         const int nwr = (in_w + 31) >> 5;
-        if constexpr (P == 2) {
+        if constexpr (P >= 2) {
             if ((NI / 4) * ((NJ + 1) / 2) >= (int)(blockDim.x >> 6)) {
                 dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
                 return;
@@ -806,10 +912,10 @@ template <int P> struct EpiRowsOut {
     const A* bias; T* out; int ld; int row0; int nrows;
     __device__ __forceinline__ void operator()(int r, int n0, const typename PT<P>::Acc& acc) const {
         if (row0 + r >= nrows) return;
-        typename PT<P>::O4 o;
+        A o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[v] = (T)((A)acc[v] + bias[n0 + v]);
-        *reinterpret_cast<typename PT<P>::O4*>(out + (size_t)(row0 + r) * ld + n0) = o;
+        for (int v = 0; v < 4; ++v) o[v] = (A)acc[v] + bias[n0 + v];
+        st4<P>(out + (size_t)(row0 + r) * ld, n0, o);
     }
 };
 
@@ -981,10 +1087,10 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_res(const GradArgs a) {
                 A s = (A)0;
                 if (j == 0xFFFF) {
 #pragma unroll 8
-                    for (int r = 0; r < R; ++r) s += (A)D[r * ld + i];
+                    for (int r = 0; r < R; ++r) s += ld1<P>(D + r * ld, i);
                 } else {
 #pragma unroll 8
-                    for (int r = 0; r < R; ++r) s = fma((A)D[r * ld + i], (A)X[r * lx + j], s);
+                    for (int r = 0; r < R; ++r) s = fma(ld1<P>(D + r * ld, i), ld1<P>(X + r * lx, j), s);
                 }
                 acc[m] += s;
             }
@@ -1126,9 +1232,9 @@ __device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, 
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const int d0 = s.dst[2 * e], d1 = s.dst[2 * e + 1];
     if (d0 >= 0) {
-        T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;
-        W[d0] = (T)x;
-        W[d1] = (T)x;
+        T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;   // rows of multiples of 32: flat indices
+        st1<P>(W, d0, (A)x);
+        st1<P>(W, d1, (A)x);
         if (s.wbuf32) {   // FP32 shadow of the weights for the energy pass
             float* W32 = reinterpret_cast<float*>(s.wbuf32) + c * s.wstride;
             W32[d0] = (float)x;
@@ -1427,7 +1533,7 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-    if constexpr (P != 2) {
+    if constexpr (P < 2) {
         if ((e = hipFuncSetAttribute((const void*)k_tower_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_tower_out<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_mlp_predict<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
@@ -1449,12 +1555,13 @@ hipError_t set_lds(size_t lds) {
         case 16: CALL(0, 16); case 32: CALL(0, 32); case 64: CALL(0, 64);     \
         case 116: CALL(1, 16); case 132: CALL(1, 32); case 164: CALL(1, 64);  \
         case 216: CALL(2, 16); case 232: CALL(2, 32); case 264: CALL(2, 64);  \
+        case 316: CALL(3, 16); case 332: CALL(3, 32); case 364: CALL(3, 64);  \
         default: return hipErrorInvalidValue;                                  \
     }
 
 #define HMC_DISPATCH_P(P, CALL)                                                \
     switch (P) {                                                               \
-        case 0: CALL(0); case 1: CALL(1); case 2: CALL(2);                     \
+        case 0: CALL(0); case 1: CALL(1); case 2: CALL(2); case 3: CALL(3);    \
         default: return hipErrorInvalidValue;                                  \
     }
 
@@ -1527,6 +1634,7 @@ hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void*
         case 0: hipLaunchKernelGGL((k_scatter_vec<0>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
         case 1: hipLaunchKernelGGL((k_scatter_vec<1>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
         case 2: hipLaunchKernelGGL((k_scatter_vec<2>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
+        case 3: hipLaunchKernelGGL((k_scatter_vec<3>), dim3(g), dim3(256), 0, s, sa, c, vec); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
