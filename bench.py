@@ -146,6 +146,60 @@ def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_di
     print(path, out["traffic_bytes_per_launch"])
 
 
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F64")
+PROFILE_CMDS["mfma"] = ("rocprofv3 --pmc " + " ".join(MFMA_COUNTERS) + " --output-format csv -d gpurun_out/pmc_mfma_{w} "
+                        "-o bench -- python bench.py --config {w} --steps 2 --warmup 1 --adapt 2 --no-cpu-baseline "
+                        "--no-ess --timing-reps 5")
+N_SIMD = 256 * 4   # MI355X: 256 compute units of 4 SIMDs
+N_XCD = 8          # the per-dispatch GRBM_GUI_ACTIVE value is summed over the 8 XCDs
+
+
+def record_mfma(workload, pmc_dir):
+    """Writes profiles/<kernel>_<workload>_mfma.txt: per tile kernel, the
+    MFMA busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of one
+    XCD times the SIMD count, as rocprof's MfmaUtil, which takes the maximum
+    of GRBM_GUI_ACTIVE over XCDs where the per-dispatch value sums them) and
+    the MFMA flops the hardware executed (MOPS x 512) against the
+    algorithmic flops."""
+    import csv
+    import glob
+    import workloads
+    w = workloads.make(workload)
+    rows = list(csv.DictReader(open(glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0])))
+    names = ["k_mlp_grad<", "k_trunk_fwd<", "k_branch_grad<", "k_trunk_bwd<", "k_update<"]
+    parts = {"k_mlp_grad<": None, "k_branch_grad<": "branch", "k_trunk_fwd<": None, "k_trunk_bwd<": None}
+    lines = [f"MFMA counters per dispatch: masked full-batch HMC, workload {workload} "
+             f"({w.precision.upper()}, {w.n_chains} chains, L={w.L})",
+             f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
+             "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
+             "  " + PROFILE_CMDS["mfma"].format(w=workload), "",
+             "busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs * 1024 SIMDs); "
+             "executed = MOPS * 512 flops (padding to the MFMA tiles included)",
+             f"{'kernel':<42}{'dispatches':>11}{'busy %':>9}{'executed GFLOP':>16}{'algorithmic GFLOP':>19}"]
+    for n in names:
+        sel = [r for r in rows if n in r["Kernel_Name"]]
+        if not sel:
+            continue
+        kname = sel[0]["Kernel_Name"].replace("void (anonymous namespace)::", "")
+        per = {}
+        for r in sel:
+            per.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        full = [d for d in per.values() if all(c in d for c in MFMA_COUNTERS)]
+        mean = {c: sum(d[c] for d in full) / len(full) for c in MFMA_COUNTERS}
+        busy = 100.0 * mean["SQ_VALU_MFMA_BUSY_CYCLES"] / max(mean["GRBM_GUI_ACTIVE"] / N_XCD * N_SIMD, 1.0)
+        ex = 512.0 * (mean["SQ_INSTS_VALU_MFMA_MOPS_F32"] + mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] +
+                      mean["SQ_INSTS_VALU_MFMA_MOPS_F64"]) / 1e9
+        alg = ""
+        if n == "k_mlp_grad<" or n == "k_branch_grad<":
+            alg = f"{algorithmic_flops(w, parts[n]) / 1e9:.3f}"
+        lines.append(f"{kname[:41]:<42}{len(full):>11}{busy:>9.2f}{ex:>16.3f}{alg:>19}")
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_OF[w.kind]}_{workload}_mfma.txt")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path)
+    print("\n".join(lines[-6:]))
+
+
 def record_trace(workload, trace_dir, bench_json=None, sens=False):
     """Writes profiles/<kernel>_<workload>_kernel_trace.txt from the
     rocprofv3 --stats summary of the benchmark command (sens: of the
@@ -469,11 +523,16 @@ def main():
                     help="time the sensitivity pass (Sec. 3.1) on --config's data instead of the sampler")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the profiles/ traffic summary for --config from rocprofv3 counter runs and exit")
+    ap.add_argument("--record-mfma", metavar="PMC_DIR",
+                    help="write the profiles/ MFMA-counter summary for --config and exit")
     ap.add_argument("--record-trace", nargs="+", metavar="TRACE_DIR [BENCH_LOG]",
                     help="write the profiles/ kernel-trace summary for --config and exit")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args.config, *args.record_traffic)
+        return
+    if args.record_mfma:
+        record_mfma(args.config, args.record_mfma)
         return
     if args.record_trace:
         record_trace(args.config, *args.record_trace[:2], sens=args.sensitivity)
