@@ -301,7 +301,9 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
 // fixed: bytes beside the slabs (staged biases, alignment).
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
               const char* env, int forced) {
-    auto fits = [&](int r) { return tower_lds(w, prec, r) + extra_per_row * r + 64 + 16 + fixed <= g_lds_cap; };
+    auto fits = [&](int r) {
+        return tower_lds(w, prec, r) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed <= g_lds_cap;
+    };
     if (forced) return fits(forced) ? forced : 0;
     if (const char* s = std::getenv(env)) {
         const int r = std::atoi(s);
@@ -530,7 +532,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.n_chains = x->C;
     g.inv_lik_var = 1.0 / (net->lik_sd * net->lik_sd);
 
-    // LDS: activation slabs [+ output-adjoint slab] + reduction scratch.
+    // LDS: activation slabs [+ output-adjoint slab] + reduction scratch +
+    // per-chain tables (TileMeta) + staged biases [+ MLP targets].
     x->lds_a = tower_lds(x->A.w, prec, x->Ra);
     if (x->kind == HMC_DEEPONET) {
         g.dg_off = (int)(x->lds_a / ts);
@@ -540,6 +543,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     x->lds_a = (x->lds_a + 15) / 16 * 16;
     g.red_off = (int)x->lds_a;
     x->lds_a += 64;
+    g.meta_lds_a = (int)x->lds_a;
+    x->lds_a += HMC_META_BYTES;
     g.bias_lds_a = (int)x->lds_a;
     x->lds_a += bias_bytes(x->A.w, prec, as);
     g.y_lds = (int)x->lds_a;
@@ -550,6 +555,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     x->nt_a = pick_threads(x->lds_a, x->tune.threads);
     if (x->kind == HMC_DEEPONET) {
         x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
+        g.meta_lds_b = (int)x->lds_b;
+        x->lds_b += HMC_META_BYTES;
         g.bias_lds_b = (int)x->lds_b;
         x->lds_b += bias_bytes(x->B.w, prec, as);
         HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
@@ -719,6 +726,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             }
         }
     }
+    if (mw_h.size() > (size_t)INT32_MAX)
+        return x->fail(HMC_EUNSUPPORTED, "selection bitmaps exceed 2^31 words");
     int* bseg_d = (int*)x->dalloc(sizeof(int) * bseg.size());
     int* dflag_d = (int*)x->dalloc(sizeof(int) * dflag.size());
     int2* mw_d = (int2*)x->dalloc(sizeof(int2) * std::max<size_t>(mw_h.size(), 1));

@@ -737,11 +737,31 @@ __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, con
     }
 }
 
-// Lowest layer of the tower with selected entries in chain c (nl: none).
-__device__ __forceinline__ int lowest_layer(const GradArgs& a, const TowerPlan& tp, int c) {
-    const int* seg = a.seg + (size_t)c * a.nseg + tp.seg0;
+// Chain c's mask tables of one tower into LDS.  Called by every thread at
+// kernel start; the kernel's first barrier publishes them, so the adjoint
+// pass reads them from LDS instead of waiting on dependent global loads
+// between its phases.
+__device__ __forceinline__ void stage_meta(const GradArgs& a, const TowerPlan& tp, int c, TileMeta* m) {
+    const int t = (int)threadIdx.x;
+    const size_t lb = (size_t)c * a.nl_total + tp.seg0;
+    if (t <= tp.nl) m->seg[t] = a.seg[(size_t)c * a.nseg + tp.seg0 + t];
+    if (t < tp.nl) {
+        m->bseg[t] = a.bseg[lb + t];
+        m->mwoff[t] = (int)a.mw_off[lb + t];
+    }
+    if (t == 0) {
+        m->o = a.offs[c];
+        m->n = (int)(a.offs[c + 1] - a.offs[c]);
+        unsigned d = 0;
+        for (int l = 0; l < tp.nl; ++l) d |= a.dflag[lb + l] ? 1u << l : 0u;
+        m->dmask = d;
+    }
+}
+
+// Lowest layer of the tower with selected entries (nl: none).
+__device__ __forceinline__ int lowest_layer(const TowerPlan& tp, const TileMeta* m) {
     for (int l = 0; l < tp.nl; ++l)
-        if (seg[l + 1] > seg[l]) return l;
+        if (m->seg[l + 1] > m->seg[l]) return l;
     return tp.nl;
 }
 
@@ -773,24 +793,23 @@ __device__ __forceinline__ void ulik_store(double* slot8, double v) {
 // Adjoint pass of one tower from the output adjoint held in slab nl: for each
 // layer from the top, the selected weight-gradient partials, then (while a
 // lower layer still has selected entries) the adjoint of the layer input.
-// lowest: lowest_layer() of the chain.  SQ: squared weight-gradient terms
-// (sensitivity pass).
+// m: the chain's tables (stage_meta, published); lowest: lowest_layer() of
+// the chain.  SQ: squared weight-gradient terms (sensitivity pass).
 template <int P, int R, bool SQ = false>
-__device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, int c, int t,
+__device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, const TileMeta* m, int t,
                                                const typename PT<P>::T* W, typename PT<P>::T* sm, int lowest) {
     typedef typename PT<P>::A A;
-    const long long o = a.offs[c];
-    const int n = (int)(a.offs[c + 1] - o);
+    const long long o = m->o;
+    const int n = m->n;
     const int* code = a.ecode + o;
-    const int* seg = a.seg + (size_t)c * a.nseg + tp.seg0;
+    const int* seg = m->seg;
     A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)t * n;
-    const int* bseg = a.bseg + (size_t)c * a.nl_total + tp.seg0;
-    const int* dflag = a.dflag + (size_t)c * a.nl_total + tp.seg0;
+    const int* bseg = m->bseg;
+    const unsigned dmask = m->dmask;
     for (int l = tp.nl - 1; l >= lowest; --l) {
-        if (dflag[l]) {
+        if (dmask & (1u << l)) {
             dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
-                               tp.wp[l + 1] >> 4, tp.wp[l] >> 4,
-                               a.mw + a.mw_off[(size_t)c * a.nl_total + tp.seg0 + l], seg[l], part);
+                               tp.wp[l + 1] >> 4, tp.wp[l] >> 4, a.mw + m->mwoff[l], seg[l], part);
             dw_partials<P, R, SQ>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
                                   part);
         } else {
@@ -832,9 +851,11 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
         for (int i = threadIdx.x; i < R * a.d_out; i += blockDim.x) ys[i] = i < nv ? yg[i] : 0.0;
     }
     const A* B = Bs - tp.bo[0];
+    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + a.meta_lds_a);
+    if constexpr (!FWD) stage_meta(a, tp, c, meta);
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
-    const int lowest = FWD ? tp.nl : lowest_layer(a, tp, c);
+    const int lowest = FWD ? tp.nl : lowest_layer(tp, meta);
     tower_hidden_forward<P, R>(tp, W, B, sm);
     EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], ys, a.d_out, t * R, a.n_rows_a,
                     a.inv_lik_var, 0.0};
@@ -842,7 +863,7 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * h.sq);
     if constexpr (!FWD) {
         __syncthreads();
-        tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
+        tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
     }
 }
 
@@ -873,6 +894,8 @@ __global__ __launch_bounds__(HMC_NT) void k_tower_sens(const GradArgs a, int tow
     stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
     const A* B = Bs - tp.bo[0];
     const T* xin = reinterpret_cast<const T*>(tower ? a.xb : a.xa);
+    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + (tower ? a.meta_lds_b : a.meta_lds_a));
+    stage_meta(a, tp, c, meta);
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], xin + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
     tower_hidden_forward<P, R>(tp, W, B, sm);
@@ -884,7 +907,7 @@ __global__ __launch_bounds__(HMC_NT) void k_tower_sens(const GradArgs a, int tow
         so[r * tp.ls[L + 1] + col] = r < nv ? sv[col] : (T)0;
     }
     __syncthreads();
-    tower_backward<P, R, true>(a, tp, c, t, W, sm, 0);
+    tower_backward<P, R, true>(a, tp, meta, t, W, sm, 0);
 }
 
 // Output of one tower at the current weights for the rows of its tile,
@@ -1141,9 +1164,11 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
     stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
     const A* B = Bs - tp.bo[0];
+    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + a.meta_lds_a);
+    if constexpr (!FWD) stage_meta(a, tp, c, meta);
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
-    const int lowest = FWD ? tp.nl : lowest_layer(a, tp, c);
+    const int lowest = FWD ? tp.nl : lowest_layer(tp, meta);
     tower_hidden_forward<P, R>(tp, W, B, sm);
     const int nvalid = a.n_rows_a - t * R;
     const T* tmc = reinterpret_cast<const T*>(a.tm) + c * a.tm_stride;
@@ -1174,7 +1199,7 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
     gemm<P, R>(ttc, a.nq_rows, a.nq_pad, pp, sm + a.dg_off, a.dg_ld, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
+    tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
 }
 
 // DeepONet trunk adjoint tile: recompute the trunk forward for the tile's
@@ -1195,16 +1220,18 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
     A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_b);
     stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
     const A* B = Bs - tp.bo[0];
+    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + a.meta_lds_b);
+    stage_meta(a, tp, c, meta);
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xb) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
-    const int lowest = lowest_layer(a, tp, c);
+    const int lowest = lowest_layer(tp, meta);
     const T* btc = reinterpret_cast<const T*>(a.btr) + c * a.bt_stride;
     tower_hidden_forward<P, R>(tp, W, B, sm);
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
     gemm<P, R>(btc, a.nu_cols, a.nu_cols, tp.wp[L + 1],
                reinterpret_cast<const T*>(a.dgt) + c * a.dgt_stride + (size_t)t * R * a.nu_cols, a.nu_cols, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, c, t, W, sm, lowest);
+    tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,6 +30,19 @@ struct TowerPlan {
     int seg0;                   // first layer of this tower in the segment table
 };
 
+// Per-chain mask tables of one tower, staged in LDS by the tile kernels
+// that run the adjoint pass (HMC_META_BYTES reserved per workgroup).
+struct TileMeta {
+    long long o;                // offs[c]: the chain's first entry
+    int n;                      // the chain's entry count
+    unsigned dmask;             // bit l: dense weight-gradient product for layer l
+    int seg[HMC_MAXL + 1];      // chain-local start of each layer's entries (and the end)
+    int bseg[HMC_MAXL];         // chain-local start of each layer's bias entries
+    int mwoff[HMC_MAXL];        // offset of each dense layer's selection bitmap in mw
+};
+#define HMC_META_BYTES 128
+static_assert(sizeof(TileMeta) <= HMC_META_BYTES, "TileMeta exceeds its LDS reservation");
+
 // Arguments of the tile kernels (forward, loss head, adjoint, masked
 // weight-gradient partials).
 struct GradArgs {
@@ -75,6 +88,7 @@ struct GradArgs {
     int red_off;                // LDS byte offset of the reduction scratch
     int bias_lds_a, bias_lds_b; // LDS byte offsets of the staged biases of towers A and B
     int y_lds;                  // LDS byte offset of the staged MLP targets of a tile [R][d_out]
+    int meta_lds_a, meta_lds_b; // LDS byte offsets of the staged per-chain tables (TileMeta) of towers A and B
     // Resident MLP kernel: weights held in LDS, several row tiles per
     // workgroup, selected-entry partials accumulated in registers.
     int w_lds_off;              // LDS offset (elements) of the weight copy
