@@ -160,7 +160,9 @@ typedef struct {
 hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc* mask,
                     const hmc_data_desc* data, uint64_t seed, void* hip_stream);
 
-/* Launch-shape choices of the gradient kernels; 0 in a field keeps the
+/* Launch-shape choices of the gradient kernels (an engineering option, not
+ * a step of the method: every choice computes the same U and gradient up to
+ * the summation order); 0 in a field keeps the
  * engine's own choice (made from the LDS footprint, the grid size and the
  * layer densities; HMC_ROWS_A, HMC_ROWS_B, HMC_THREADS and HMC_DW in the
  * environment override it when the field is 0). */
@@ -257,7 +259,7 @@ hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
  * products on squared operands on the device, one adjoint pass per output
  * (MLP), per query point (DeepONet branch, seeded with the trunk features)
  * and per function (DeepONet trunk, seeded with the branch features); BF16
- * networks are evaluated in FP32, FP64 networks in FP64.  s2: host
+ * and BF16X3 networks are evaluated in FP32, FP64 networks in FP64.  s2: host
  * [n_params] FP64, written on success.  net->prior_sd and net->lik_sd must
  * be valid but are not used.  Synchronous; hip_stream as for hmc_init.
  * Errors: HMC_EINVAL (NULL pointers, sizes, negative or non-finite sigma),
@@ -276,8 +278,8 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
  * [n_q][d_y] (v not read), outputs [n_u][n_q].  mean (host, output shape,
  * required) receives the mean of the network outputs over the samples and
  * var (host, same shape, or NULL) their variance (1/n_samples, no Bessel
- * correction), both accumulated in FP64.  BF16 engines evaluate through
- * their FP32 weight shadow.  The engine's chain state is unchanged.
+ * correction), both accumulated in FP64.  BF16 and BF16X3 engines evaluate
+ * through their FP32 weight shadow.  The engine's chain state is unchanged.
  * Synchronous.  Errors: HMC_EINVAL (chain, sizes, NULL pointers), HMC_ENOMEM,
  * HMC_EDEVICE. */
 hmc_status hmc_predict(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t n_samples,
