@@ -718,6 +718,81 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     }
 }
 
+// Dense weight-gradient tile for BF16 operands with interleaved blocks, so
+// that a lane's K values (one per tile row) come from vector reads.  A unit
+// covers output rows i0 .. i0 + 63 and input columns j0 .. j0 + 31 as 4 x 2
+// MFMA blocks; block (bi, bj) holds rows i0 + 4 m + bi and columns
+// j0 + 2 n + bj (m, n < 16).  For each of its eight K slots r lane (g, li)
+// then needs delta[r][i0 + 4 li .. i0 + 4 li + 3] (one 8-byte read serves
+// the four row blocks) and a[r][j0 + 2 li, j0 + 2 li + 1] (one 4-byte read
+// serves the two column blocks): two LDS reads per K slot for eight blocks,
+// against six scalar reads for the non-interleaved 4 x 2 tile.  Output
+// layout: lane (g, li) holds rows m = 4 g + v of column n = li, i.e. entry
+// (i0 + 16 g + 4 v + bi, j0 + 2 li + bj).  The unit's 32 columns are one
+// word of the selection bitmap.  Requires the padded output width to be a
+// multiple of 64 and R a multiple of 32 (the padded input width is a
+// multiple of 32 for BF16).
+template <int R>
+__device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf16* X, int lx, int out_w, int NI64,
+                                            int NJ32, const int2* __restrict__ mw, int nwr, int kbase,
+                                            float* __restrict__ part) {
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    static_assert(R % 32 == 0, "K chunks of 32 tile rows");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const int nwave = (int)(blockDim.x >> 6);
+    for (int u = wave; u < NI64 * NJ32; u += nwave) {
+        const int ui = u / NJ32, w = u - ui * NJ32;   // w: the bitmap word of columns 32 w .. 32 w + 31
+        const int i0 = ui * 64, j0 = w * 32;
+        int2 tw[4][4];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * g + 4 * v + bi;
+                tw[bi][v] = (i < out_w && w < nwr) ? mw[(size_t)i * nwr + w] : make_int2(0, 0);
+            }
+        f4v acc[4][2];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) acc[bi][0] = acc[bi][1] = f4v{};
+#pragma unroll
+        for (int k0 = 0; k0 < R; k0 += 32) {
+            const int r0 = k0 + g * 8;
+            b4v dv[8];
+            b2v xv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                dv[e] = *reinterpret_cast<const b4v*>(D + (r0 + e) * ld + i0 + 4 * li);
+                xv[e] = *reinterpret_cast<const b2v*>(X + (r0 + e) * lx + j0 + 2 * li);
+            }
+            b8v fa[4], fb[2];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi) fa[bi][e] = dv[e][bi];
+                fb[0][e] = xv[e][0];
+                fb[1][e] = xv[e][1];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) mma1(acc[bi][bj], fa[bi], fb[bj], 0);
+        }
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const unsigned bits = (unsigned)tw[bi][v].x;
+                const int kb = kbase + tw[bi][v].y;
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    const unsigned sel = 1u << (2 * li + bj);
+                    if (bits & sel) part[kb + __popc(bits & (sel - 1u))] = acc[bi][bj][v];
+                }
+            }
+    }
+}
+
 template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
                                          int out_w, int in_w, int NI, int NJ, const int2* mw, int kbase,
@@ -729,6 +804,12 @@ __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, con
         const int nwr = (in_w + 31) >> 5;
         if constexpr (P >= 2) {
             if ((NI / 4) * ((NJ + 1) / 2) >= (int)(blockDim.x >> 6)) {
+                if constexpr (P == 2 && !SQ) {
+                    if (NI % 4 == 0 && NJ % 2 == 0) {
+                        dw_dense_il<R>(D, ld, X, lx, out_w, NI / 4, NJ / 2, mw, nwr, kbase, part);
+                        return;
+                    }
+                }
                 dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
                 return;
             }
