@@ -581,9 +581,10 @@ def main():
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAK[DTYPE[w.precision]]
     kname = KERNEL_OF[w.kind]
+    traffic = recorded_traffic(kname, w.name)
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": recorded_traffic(kname, w.name), "kernel": kname,
-            "kernel_ms": dom_ms, "flops_per_launch": flops}
+            "traffic": traffic, "kernel": kname, "kernel_ms": dom_ms, "flops_per_launch": flops,
+            "hbm_gbps": traffic / (dom_ms * 1e-3) / 1e9 if traffic else None}
     # the whole gradient evaluation: every tile kernel plus the partial sums
     grad_ms = sum(ms)
     grad_tf = algorithmic_flops(w) / (grad_ms * 1e-3) / 1e12
@@ -598,6 +599,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3,
+        "us_per_leapfrog_step": dt / args.steps / L * 1e6,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
