@@ -227,18 +227,19 @@ hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hm
 
 // ----------------------------------------------------------------- planning
 
-// Threads per workgroup of a tile kernel.  A workgroup whose LDS leaves room
-// for a second one on the CU runs with 4 waves (two workgroups per CU hide
-// each other's barriers); one that holds the CU's LDS alone runs with 8 waves
-// so that the CU still has 8 waves in flight.  A tuning value (256 or 512)
-// or else HMC_THREADS overrides the choice.
-int pick_threads(size_t lds, int forced) {
+// Threads per workgroup of a tile kernel: 512 (8 waves).  Measured on every
+// named workload it is as fast as or faster than 256, also where two
+// workgroups share a CU's LDS (the FP32 MLP 32.1 -> 31.8 us, the DeepONet
+// trunk adjoint 54 -> 50 us; the BF16 kernels that fill a CU's LDS alone lose
+// a third of their speed at 256).  A tuning value (256 or 512) or else
+// HMC_THREADS overrides it.
+int pick_threads(size_t /*lds*/, int forced) {
     if (forced == 256 || forced == 512) return forced;
     if (const char* s = std::getenv("HMC_THREADS")) {
         const int t = std::atoi(s);
         if (t == 256 || t == 512) return t;
     }
-    return 2 * lds <= g_lds_cap ? 256 : 512;
+    return 512;
 }
 
 size_t tower_lds(const std::vector<int>& w, int prec, int R) {
