@@ -1089,6 +1089,53 @@ hmc_status hmc_autotune(const hmc_net_desc* net, const hmc_mask_desc* mask, cons
     return HMC_OK;
 }
 
+namespace {
+// Factor of the Gram matrix G = F^T F of the rows of F (rows x p, row stride
+// ld): vectors l_m with sum_m l_m l_m^T = G, by Cholesky with diagonal
+// pivoting (G is positive semi-definite, of rank at most min(rows, p)),
+// stopping when the largest remaining diagonal entry falls below 1e-13 of
+// the largest initial one.  Returns the vectors as rows of [rank][ld]
+// (entries past p zero).  For any vectors a_r,
+// sum_rows (f_row . a)^2 = a^T G a = sum_m (l_m . a)^2, so the l_m seed
+// the same sum of squared output derivatives in rank passes.
+std::vector<double> gram_factor(const std::vector<double>& F, long long rows, int p, int ld, int& rank) {
+    std::vector<double> G((size_t)p * p, 0.0);
+    for (long long r = 0; r < rows; ++r) {
+        const double* f = F.data() + (size_t)r * ld;
+        for (int i = 0; i < p; ++i)
+            for (int j = i; j < p; ++j) G[(size_t)i * p + j] += f[i] * f[j];
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < i; ++j) G[(size_t)i * p + j] = G[(size_t)j * p + i];
+    std::vector<double> d(p), L;
+    std::vector<char> used(p, 0);
+    double d0 = 0.0;
+    for (int i = 0; i < p; ++i) d0 = std::max(d0, d[i] = G[(size_t)i * p + i]);
+    rank = 0;
+    while (rank < p) {
+        int piv = -1;
+        for (int i = 0; i < p; ++i)
+            if (!used[i] && (piv < 0 || d[i] > d[piv])) piv = i;
+        if (piv < 0 || !(d[piv] > 1e-13 * d0)) break;
+        std::vector<double> l((size_t)ld, 0.0);
+        const double lp = std::sqrt(d[piv]);
+        l[piv] = lp;
+        for (int j = 0; j < p; ++j) {
+            if (used[j] || j == piv) continue;
+            double v = G[(size_t)j * p + piv];
+            for (int m = 0; m < rank; ++m) v -= L[(size_t)m * ld + j] * L[(size_t)m * ld + piv];
+            l[j] = v / lp;
+        }
+        used[piv] = 1;
+        for (int j = 0; j < p; ++j)
+            if (!used[j]) d[j] -= l[j] * l[j];
+        L.insert(L.end(), l.begin(), l.end());
+        ++rank;
+    }
+    return L;
+}
+}  // namespace
+
 hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, const double* sigma, double* s2,
                            void* hip_stream) {
     g_init_error.clear();
@@ -1158,12 +1205,40 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
         const long long nb = x->B.flat0;   // entries of the branch tower come first, b0 last
         if (e == hipSuccess) e = hmc_launch_tower_out(P_, x->Rb, x->nt_b, g, 1, seed_a, wpo, x->grid_b, x->lds_b, x->stream);
         if (e == hipSuccess) e = hmc_launch_tower_out(P_, x->Ra, x->nt_a, g, 0, seed_b, wpo, x->grid_a, x->lds_a, x->stream);
-        for (long long q = 0; q < rows_b && e == hipSuccess; ++q) {
+        // When a tower has more feature rows than features, seed its passes
+        // with the factor of the features' Gram matrix instead of the rows:
+        // the same sums in at most p passes (1000 trunk passes become 128 on
+        // the antiderivative workload).
+        long long npass_a = rows_b, npass_b = rows_a;
+        auto refactor = [&](void* seed, long long rows, long long& npass) {
+            const int p = x->A.w.back();
+            if (e != hipSuccess || rows <= p) return;
+            std::vector<unsigned char> raw((size_t)rows * wpo * ts);
+            e = hipMemcpyAsync(raw.data(), seed, raw.size(), hipMemcpyDeviceToHost, x->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+            if (e != hipSuccess) return;
+            std::vector<double> F((size_t)rows * wpo);
+            for (size_t i = 0; i < F.size(); ++i) {
+                if (ts == 8) std::memcpy(&F[i], &raw[i * 8], 8);
+                else { float f; std::memcpy(&f, &raw[i * 4], 4); F[i] = f; }
+            }
+            int rank = 0;
+            const std::vector<double> L = gram_factor(F, rows, p, wpo, rank);
+            std::vector<unsigned char> h((size_t)std::max(rank, 1) * wpo * ts, 0);
+            for (int m = 0; m < rank; ++m)
+                for (int k = 0; k < p; ++k) put_t(h, P_, (size_t)m * wpo + k, L[(size_t)m * wpo + k]);
+            e = hipMemcpyAsync(seed, h.data(), h.size(), hipMemcpyHostToDevice, x->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(x->stream);   // h is released on return
+            npass = rank;
+        };
+        refactor(seed_a, rows_b, npass_a);
+        refactor(seed_b, rows_a, npass_b);
+        for (long long q = 0; q < npass_a && e == hipSuccess; ++q) {
             e = hmc_launch_tower_sens(P_, x->Ra, x->nt_a, g, 0, (const char*)seed_a + (size_t)q * wpo * ts, x->grid_a,
                                       x->lds_a, x->stream);
             if (e == hipSuccess) e = hmc_launch_sens_reduce(P_, g.part, x->tiles_a, P, 0, nb, acc, sig, 0.0, nullptr, x->stream);
         }
-        for (long long j = 0; j < rows_a && e == hipSuccess; ++j) {
+        for (long long j = 0; j < npass_b && e == hipSuccess; ++j) {
             e = hmc_launch_tower_sens(P_, x->Rb, x->nt_b, g, 1, (const char*)seed_b + (size_t)j * wpo * ts, x->grid_b,
                                       x->lds_b, x->stream);
             if (e == hipSuccess)

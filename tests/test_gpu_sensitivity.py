@@ -103,3 +103,24 @@ def test_zero_sigma_gives_zero_sensitivity():
     sigma[::7] = 0.0
     got = _gpu(w.widths_a, w.theta0, sigma, w.x, "fp32")
     assert np.all(got[::7] == 0.0) and np.all(got[1::7] > 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_deeponet_gram_seeded_passes_match_oracle(prec):
+    """More functions and query points than latent features (40 and 30
+    against p = 16): both towers' passes are seeded with the factor of the
+    feature Gram matrix instead of one pass per row; the sums must not
+    change."""
+    from oracle import network as on
+    from paper_2507_14652_amd import sensitivities
+    rng = np.random.default_rng(12)
+    wa, wb = [20, 32, 16], [1, 24, 16]
+    P = on.net_size("deeponet", wa, wb)
+    mu = rng.normal(0, 0.3, P)
+    sigma = rng.uniform(0.05, 0.3, P)
+    u = rng.normal(0, 1, (40, 20))
+    yq = rng.uniform(0, 1, (30, 1))
+    got = sensitivities(kind="deeponet", widths_a=wa, widths_b=wb, theta0=mu, sigma=sigma, u=u, yq=yq, precision=prec)
+    ref = osen.sensitivities("deeponet", wa, wb, mu, sigma, {"u": u, "yq": yq})
+    print(f"gram-seeded deeponet {prec}: rel {np.linalg.norm(got - ref) / np.linalg.norm(ref):.2e}")
+    _check(got, ref, prec)
