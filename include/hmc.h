@@ -258,7 +258,10 @@ hmc_status hmc_time_kernels(hmc_ctx* ctx, int32_t reps, double* ms);
  * of each input (their variances add).  Every layer runs as MFMA tile
  * products on squared operands on the device, one adjoint pass per output
  * (MLP), per query point (DeepONet branch, seeded with the trunk features)
- * and per function (DeepONet trunk, seeded with the branch features); BF16
+ * and per function (DeepONet trunk, seeded with the branch features); a
+ * DeepONet tower with more such rows than latent features p is seeded with
+ * the p or fewer vectors of a factor of the features' Gram matrix instead,
+ * which gives the same sums; BF16
  * and BF16X3 networks are evaluated in FP32, FP64 networks in FP64.  s2: host
  * [n_params] FP64, written on success.  net->prior_sd and net->lik_sd must
  * be valid but are not used.  Synchronous; hip_stream as for hmc_init.
