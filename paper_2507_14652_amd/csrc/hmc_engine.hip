@@ -296,9 +296,12 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
     return 0;
 }
 
-// Largest row tile whose LDS footprint fits, shrunk while the grid would
-// leave most compute units idle.  A tuning value (16, 32 or 64; 0 when it
-// does not fit) or else HMC_ROWS_A / HMC_ROWS_B overrides it.
+// Largest row tile whose LDS footprint fits, halved while the grid has
+// fewer workgroups than the 256 compute units (smaller tiles re-read the
+// weights more often, so a grid of one 512-thread workgroup per compute unit
+// is enough: the DeepONet trunk adjoint runs 50 -> 46 us at 32 rows instead
+// of 16).  A tuning value (16, 32 or 64; 0 when it does not fit) or else
+// HMC_ROWS_A / HMC_ROWS_B overrides it.
 // fixed: bytes beside the slabs (staged biases, alignment).
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
               const char* env, int forced) {
@@ -313,7 +316,7 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
     int best = 0;
     for (int R : {64, 32, 16})
         if (fits(R)) { best = R; break; }
-    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 512 && fits(best / 2)) best /= 2;
+    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 256 && fits(best / 2)) best /= 2;
     return best;
 }
 
