@@ -906,6 +906,58 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     }
 }
 
+// MLP output layer and head in FP64 for FP32 and split-BF16 products with
+// few outputs: F = W_L a + b as FP64 dot products of the stored activations
+// and weights (eight lanes per (row, output), then a butterfly), residual,
+// squared residuals and delta = (F - y) / lik_sd^2 into slab L + 1 (zero for
+// padded outputs and rows past the data).  Near the mode the residual is a
+// small difference of values of order one, and an FP32 accumulation of the
+// product would put most of its error there (2e-4 of the residual on the
+// 256-wide MLP), and so into U, the output adjoint and the gradient.
+// Returns the thread's sum of squared residuals.
+template <int P, int R>
+__device__ __forceinline__ double head_fp64(const GradArgs& a, const TowerPlan& tp, const typename PT<P>::T* W,
+                                            const typename PT<P>::A* B, typename PT<P>::T* sm, const double* ys,
+                                            int t) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    const int L = tp.nl - 1;
+    const T* X = sm + tp.lo[L];
+    const T* Wl = W + tp.wo[L];
+    T* D = sm + tp.lo[L + 1];
+    const int K = tp.wp[L], NP = tp.wp[L + 1], ldx = tp.ls[L], ldd = tp.ls[L + 1], d_out = a.d_out;
+    const A* bias = B + tp.bo[L];
+    for (int i = threadIdx.x; i < R * NP; i += blockDim.x) {
+        const int r = i / NP, n = i - r * NP;
+        if (n >= d_out) st1<P>(D + r * ldd, n, (A)0);
+    }
+    double sq = 0.0;
+    const int sub = (int)threadIdx.x & 7, groups = (int)blockDim.x >> 3;
+    // every lane runs the same number of iterations, so the butterflies see
+    // all eight lanes of each group
+    for (int base = 0; base < R * d_out; base += groups) {
+        const int pr = base + ((int)threadIdx.x >> 3);
+        const int r = pr / d_out, n = pr - r * d_out;
+        const bool in = pr < R * d_out;
+        double acc = 0.0;
+        if (in)
+            for (int k = sub; k < K; k += 8)
+                acc = fma((double)ld1<P>(X + r * ldx, k), (double)ld1<P>(Wl + (size_t)n * K, k), acc);
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 4, 64);
+        if (in && sub == 0) {
+            A d = (A)0;
+            if (t * R + r < a.n_rows_a) {
+                const double res = (acc + (double)bias[n]) - ys[r * d_out + n];
+                sq += res * res;
+                d = (A)(res * a.inv_lik_var);
+            }
+            st1<P>(D + r * ldd, n, d);
+        }
+    }
+    return sq;
+}
+
 // ---------------------------------------------------------------------------
 // MLP: forward, head and adjoint of one (chain, row tile).
 // FWD = true: forward pass and likelihood partials only (the energy pass),
@@ -938,10 +990,21 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     __syncthreads();
     const int lowest = FWD ? tp.nl : lowest_layer(tp, meta);
     tower_hidden_forward<P, R>(tp, W, B, sm);
-    EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], ys, a.d_out, t * R, a.n_rows_a,
-                    a.inv_lik_var, 0.0};
-    gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
-    ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * h.sq);
+    double sq = 0.0;
+    bool head_done = false;
+    if constexpr (P == 1 || P == 3) {
+        if (a.d_out <= 4) {
+            sq = head_fp64<P, R>(a, tp, W, B, sm, ys, t);
+            head_done = true;
+        }
+    }
+    if (!head_done) {
+        EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], ys, a.d_out, t * R, a.n_rows_a,
+                        a.inv_lik_var, 0.0};
+        gemm<P, R>(W + tp.wo[L], tp.wp[L], tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
+        sq = h.sq;
+    }
+    ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * sq);
     if constexpr (!FWD) {
         __syncthreads();
         tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);

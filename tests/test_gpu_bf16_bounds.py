@@ -16,8 +16,9 @@ different stiffness: on the DeepONet split BF16 decides like exact HMC
 differs in 57%; the last-layer posterior of the 16,384-row MLP is far
 stiffer (largest precision eigenvalue 2.3e8, and near the mode the gradient
 is about 1e-3 of the sums it is made of), so the gradient error of split
-BF16 products already moves the energy by tens (63% of the decisions
-differ) and only FP32 keeps the acceptance rate within 1 point there.
+BF16 products already moves the energy by tens (61% of the decisions
+differ) and only FP32 keeps the acceptance rate within 1 point there (0.6%
+of the decisions differ, with the output layer and residual in FP64).
 """
 
 import math
@@ -76,7 +77,7 @@ def test_synced_trajectories_against_the_exact_leapfrog(label, make, prec):
     # (p99 of the position error, fraction of differing decisions, acceptance difference); None: not bounded
     bounds = {
         "fp64": (1e-12, 0.002, 0.002),
-        "fp32": (1e-5, 0.01 if deep else 0.04, 0.01 if deep else 0.02),
+        "fp32": (1e-5, 0.01 if deep else 0.015, 0.01),
         "bf16x3": (1e-4 if deep else 1e-5, 0.01 if deep else None, 0.01 if deep else None),
         "bf16": (0.05, None, None),
     }[prec]
