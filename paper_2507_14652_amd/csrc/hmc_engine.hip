@@ -563,6 +563,22 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->lds_b += HMC_META_BYTES;
         g.bias_lds_b = (int)x->lds_b;
         x->lds_b += bias_bytes(x->B.w, prec, as);
+        // the trunk adjoint tile's rows of the transposed output adjoint (the
+        // operand of dT = dG^T B, reduced over all nu_cols functions) staged
+        // in LDS when they fit beside the tower: one bulk load, issued at
+        // kernel start, in place of every wave reading them from global
+        // memory inside the product
+        {
+            const size_t off = (x->lds_b + 15) / 16 * 16;
+            const int ld = g.nu_cols + lpad_of(prec);
+            const size_t need = (size_t)x->Rb * ld * ts;
+            g.dgt_stage = off + need <= g_lds_cap ? 1 : 0;
+            if (g.dgt_stage) {
+                g.dgt_lds = (int)off;
+                g.dgt_lds_ld = ld;
+                x->lds_b = off + need;
+            }
+        }
         HMC_HIP(x, hmc_set_lds_limit(prec, x->Rb, g_lds_cap));
         x->nt_b = pick_threads(x->lds_b, x->tune.threads);
     }

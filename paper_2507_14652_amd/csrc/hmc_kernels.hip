@@ -35,6 +35,7 @@
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 typedef __bf16 b16v __attribute__((ext_vector_type(16), aligned(16)));
@@ -1324,14 +1325,12 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     EpiCombine<P> ec{sm + a.dg_off, a.dg_ld, reinterpret_cast<T*>(a.dgt) + c * a.dgt_stride, a.nu_cols, t * R,
                      a.target, a.nq, nvalid, t * R, b0, a.inv_lik_var, !FWD, 0.0, 0.0};
     gemm<P, R>(tmc, pp, pp, a.nq_pad, sm + tp.lo[L + 1], tp.ls[L + 1], ec);
-    const double sq = block_sum(ec.sq, red);
-    if constexpr (FWD) {
-        if (threadIdx.x == 0) a.ulik[((size_t)c * a.tiles_a + t) * 8] = 0.5 * a.inv_lik_var * sq;
-        return;
-    }
+    // likelihood partials one per wave (summed in a fixed order with the
+    // tile's other slots when the trajectory step ends)
+    ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * ec.sq);
+    if constexpr (FWD) return;
     const double sdg = block_sum(ec.sdg, red);
     if (threadIdx.x == 0) {
-        a.ulik[((size_t)c * a.tiles_a + t) * 8] = 0.5 * a.inv_lik_var * sq;
         const long long o = a.offs[c];
         const int n = (int)(a.offs[c + 1] - o);
         const int* seg = a.seg + (size_t)c * a.nseg;
@@ -1370,10 +1369,47 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
     __syncthreads();
     const int lowest = lowest_layer(tp, meta);
     const T* btc = reinterpret_cast<const T*>(a.btr) + c * a.bt_stride;
+    // The tile's R rows of dG^T, a contiguous block of R * nu_cols values:
+    // with dgt_stage, the first XPRE 16-byte chunks of each thread are loaded
+    // now, so that their latency overlaps the forward recompute, and stored
+    // to LDS (rows padded to dgt_lds_ld) after it; the rest is copied there.
+    const T* dgt_tile = reinterpret_cast<const T*>(a.dgt) + c * a.dgt_stride + (size_t)t * R * a.nu_cols;
+    constexpr int XPRE = 8;
+    const int nthr = (int)blockDim.x;
+    const int rowc = a.nu_cols * (int)sizeof(T) / 16;     // 16-byte chunks per row
+    const int nch = R * rowc;
+    u4v xr[XPRE];
+    if (a.dgt_stage) {
+#pragma unroll
+        for (int j = 0; j < XPRE; ++j) {
+            const int e = (int)threadIdx.x + j * nthr;
+            if (e < nch) xr[j] = reinterpret_cast<const u4v*>(dgt_tile)[e];
+        }
+    }
     tower_hidden_forward<P, R>(tp, W, B, sm);
+    const T* X = dgt_tile;
+    int ldx = a.nu_cols;
+    if (a.dgt_stage) {
+        unsigned char* xl = smem + a.dgt_lds;
+        const int ldb = a.dgt_lds_ld * (int)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < XPRE; ++j) {
+            const int e = (int)threadIdx.x + j * nthr;
+            if (e < nch) {
+                const int r = e / rowc;
+                *reinterpret_cast<u4v*>(xl + r * ldb + (e - r * rowc) * 16) = xr[j];
+            }
+        }
+        for (int e = (int)threadIdx.x + XPRE * nthr; e < nch; e += nthr) {
+            const int r = e / rowc;
+            *reinterpret_cast<u4v*>(xl + r * ldb + (e - r * rowc) * 16) = reinterpret_cast<const u4v*>(dgt_tile)[e];
+        }
+        __syncthreads();
+        X = reinterpret_cast<const T*>(xl);
+        ldx = a.dgt_lds_ld;
+    }
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
-    gemm<P, R>(btc, a.nu_cols, a.nu_cols, tp.wp[L + 1],
-               reinterpret_cast<const T*>(a.dgt) + c * a.dgt_stride + (size_t)t * R * a.nu_cols, a.nu_cols, es);
+    gemm<P, R>(btc, a.nu_cols, a.nu_cols, tp.wp[L + 1], X, ldx, es);
     __syncthreads();
     tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
 }

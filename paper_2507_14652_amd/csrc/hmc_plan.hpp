@@ -89,6 +89,9 @@ struct GradArgs {
     int bias_lds_a, bias_lds_b; // LDS byte offsets of the staged biases of towers A and B
     int y_lds;                  // LDS byte offset of the staged MLP targets of a tile [R][d_out]
     int meta_lds_a, meta_lds_b; // LDS byte offsets of the staged per-chain tables (TileMeta) of towers A and B
+    int dgt_stage;              // 1: the trunk adjoint tile stages its rows of dgt in LDS (at dgt_lds, row
+    int dgt_lds, dgt_lds_ld;    //   stride dgt_lds_ld elements) before the product dT = dG^T B; 0: reads them
+                                //   from global memory
     // Resident MLP kernel: weights held in LDS, several row tiles per
     // workgroup, selected-entry partials accumulated in registers.
     int w_lds_off;              // LDS offset (elements) of the weight copy
