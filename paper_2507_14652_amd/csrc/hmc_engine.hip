@@ -669,23 +669,31 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // Per layer: where its bias entries start, and whether its weight partials
     // come from a dense tile product (MFMA over the tile rows, selected
     // entries picked through the layer's selection bitmap) or from per-entry
-    // sums (two LDS reads and one FMA per row and entry).  The dense product
-    // costs in proportion to in*out, the sums in proportion to the selected
-    // count.  Measured on MI355X: in BF16 (MFMA 16x faster than FP32) the
-    // dense product halves the 256-wide MLP at 1-20% density; in FP32 and
-    // FP64 it is slower than the sums at 10% density on 64-wide layers, and
-    // on narrow layers (one 16-wide block) the padded product is slower in
-    // every precision.  So the dense product is used for BF16 layers at least
-    // 64 wide on both sides with density >= 1/128.  HMC_DW=dense or
-    // HMC_DW=gather forces one path for every layer that the dense product
-    // supports (tile rows a multiple of the MFMA K chunk).
+    // sums (two LDS reads and one FMA per row and entry).  Per tile, the
+    // dense product costs in proportion to in*out (mostly the selection
+    // through the bitmap, whatever the tile height), the sums in proportion
+    // to (selected count) * R.  Measured on MI355X: in BF16 (MFMA 16x faster
+    // than FP32) the dense product halves the 256-wide MLP at 1-20% density
+    // (R = 64) and is faster on the 128-wide DeepONet branch at 5% (R = 64,
+    // 158 against 172 us), but the sums are faster on the trunk tiles of 32
+    // rows (5% on the 128-wide trunk: 37.6 against 39.2 us; 2% on the
+    // 512-wide one: 0.47 against 0.64 ms); in FP32 and FP64 the product is
+    // slower than the sums at 10% density on 64-wide layers, and on narrow
+    // layers (one 16-wide block) the padded product is slower in every
+    // precision.  So the dense product is used for BF16 layers at least 64
+    // wide on both sides where (selected count) * R >= DWK * in * out.  Split
+    // BF16 sums read two values per operand, and there the product stays the
+    // faster path on 32-row tiles (DeepONet branch at 5%: 371 against
+    // 384 us), so it keeps the plain density rule (>= 1/128) on such layers.
+    // HMC_DW=dense or HMC_DW=gather forces one path for every layer that the
+    // dense product supports (tile rows a multiple of the MFMA K chunk).
     const int nlt = la + lb;
     std::vector<int> bseg((size_t)x->C * std::max(nlt, 1)), dflag((size_t)x->C * std::max(nlt, 1));
     const char* dwenv = std::getenv("HMC_DW");
     const bool force_dense = x->tune.dw == 2 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "dense"));
     const bool force_gather = x->tune.dw == 1 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "gather"));
     const int kch = pad_of(prec);
-    const int thr = 128;   // BF16: dense when density >= 1/thr
+    const long long DWK = 2;   // BF16: dense when density * R >= DWK
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
         const int64_t* id = mask->idx + o;
@@ -698,8 +706,10 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             const long long nw = b - seg[(size_t)c * nseg + L];
             const int R = L < la ? x->Ra : x->Rb;
             const bool can = nw > 0 && R % kch == 0;
-            const bool autod = (prec == HMC_BF16 || prec == HMC_BF16X3) && tp.w[l] >= 64 && tp.w[l + 1] >= 64 &&
-                               nw * thr >= (long long)tp.w[l] * tp.w[l + 1];
+            const long long area = (long long)tp.w[l] * tp.w[l + 1];
+            const bool wide = tp.w[l] >= 64 && tp.w[l + 1] >= 64;
+            const bool autod = wide && ((prec == HMC_BF16 && nw * R >= DWK * area) ||
+                                        (prec == HMC_BF16X3 && nw * 128 >= area));
             const bool dense = can && !force_gather && (force_dense || autod || x->force_dense);
             dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
         }
