@@ -360,12 +360,15 @@ hmc_status launch_refresh(hmc_ctx* x, hipStream_t s) {
 
 // Leapfrog part of a trajectory: begin (refresh or injected momentum, first
 // half kick and drift), then L gradient evaluations each followed by a kick;
-// all but the last kick are full steps followed by a drift.
+// all but the last kick are full steps followed by a drift.  The FP32 weight
+// copy of the energy pass is written by the first drift (k_traj_begin) and
+// the last one only: the energy pass reads it at theta_L.
 hmc_status launch_leapfrog(hmc_ctx* x, const StateArgs& sa, int L, hipStream_t s) {
     HMC_HIP(x, hmc_launch_traj_begin(x->prec, sa, s));
     for (int t = 1; t <= L; ++t) {
         HMC_TRY(launch_grad(x, s));
-        HMC_HIP(x, hmc_launch_update(x->prec, sa, t < L ? UPD_KICK_DRIFT : UPD_HALF_KICK, update_grid(x), s));
+        const int mode = t == L ? UPD_HALF_KICK : t == L - 1 ? UPD_KICK_DRIFT_LAST : UPD_KICK_DRIFT;
+        HMC_HIP(x, hmc_launch_update(x->prec, sa, mode, update_grid(x), s));
     }
     return launch_energy(x, s);
 }

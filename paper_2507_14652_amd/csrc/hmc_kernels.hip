@@ -1417,15 +1417,17 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
 // ---------------------------------------------------------------------------
 // Per-entry state kernels.
 
+// w32: also into the FP32 weight copy of the energy pass (when there is one).
 template <int P>
-__device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, typename PT<P>::S x) {
+__device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, typename PT<P>::S x,
+                                        bool w32 = true) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     const int d0 = s.dst[2 * e], d1 = s.dst[2 * e + 1];
     if (d0 >= 0) {
         T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;   // rows of multiples of 32: flat indices
         st1<P>(W, d0, (A)x);
         st1<P>(W, d1, (A)x);
-        if (s.wbuf32) {   // FP32 shadow of the weights for the energy pass
+        if (w32 && s.wbuf32) {   // FP32 shadow of the weights for the energy pass
             float* W32 = reinterpret_cast<float*>(s.wbuf32) + c * s.wstride;
             W32[d0] = (float)x;
             W32[d1] = (float)x;
@@ -1476,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode) {
     const S m = s.minv ? reinterpret_cast<const S*>(s.minv)[o + k] : (S)1;
     x = x + e * m * p;
     th[k] = x;
-    scatter<P>(s, c, o + k, x);
+    scatter<P>(s, c, o + k, x, mode == UPD_KICK_DRIFT_LAST);
 }
 
 __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0, unsigned long long k1) {

@@ -141,5 +141,9 @@ struct StateArgs {
     long long* n_div;           // [C]
 };
 
-enum { UPD_GRAD = 0, UPD_KICK_DRIFT = 1, UPD_HALF_KICK = 2 };
+// UPD_KICK_DRIFT_LAST: the last kick and drift of a trajectory, which also
+// writes the positions into the FP32 weight copy read by the energy pass
+// (earlier drifts leave that copy alone: nothing reads it before the drift
+// to theta_L).
+enum { UPD_GRAD = 0, UPD_KICK_DRIFT = 1, UPD_HALF_KICK = 2, UPD_KICK_DRIFT_LAST = 3 };
 enum { END_ENERGY = 0, END_TRAJ = 1, END_METROPOLIS = 2 };
