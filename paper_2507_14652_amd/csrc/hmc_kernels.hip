@@ -1418,11 +1418,11 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
 // Per-entry state kernels.
 
 // w32: also into the FP32 weight copy of the energy pass (when there is one).
+// d0, d1: the entry's destinations s.dst[2e], s.dst[2e + 1].
 template <int P>
-__device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, typename PT<P>::S x,
-                                        bool w32 = true) {
+__device__ __forceinline__ void scatter_to(const StateArgs& s, int c, int d0, int d1, typename PT<P>::S x,
+                                           bool w32) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
-    const int d0 = s.dst[2 * e], d1 = s.dst[2 * e + 1];
     if (d0 >= 0) {
         T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;   // rows of multiples of 32: flat indices
         st1<P>(W, d0, (A)x);
@@ -1436,39 +1436,75 @@ __device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, 
         reinterpret_cast<A*>(s.bbuf)[c * s.bstride + (-d0 - 1)] = (A)x;
     }
 }
+template <int P>
+__device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, typename PT<P>::S x,
+                                        bool w32 = true) {
+    scatter_to<P>(s, c, s.dst[2 * e], s.dst[2 * e + 1], x, w32);
+}
 
 // Sum of the per-tile partials in tile order, plus the prior term, then the
-// kick (and drift + scatter) of the leapfrog step.
+// kick (and drift + scatter) of the leapfrog step.  sub (a power of two, at
+// most 8) threads per entry: thread sl of an entry sums the tiles
+// t = sl (mod sub) with eight independent partial sums (so eight loads are
+// in flight), and with sub > 1 the sub-lane sums meet in LDS and are added
+// in sub-lane order.  Every order is fixed, so the result does not depend
+// on timing.  More sub-lanes serve small grids, where the tile loop's load
+// latency, not bandwidth, sets the time.
 template <int P>
-__global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode) {
+__global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode, int sub) {
     typedef typename PT<P>::A A; typedef typename PT<P>::S S;
+    __shared__ A red[256];
     const int c = blockIdx.y;
     if (!s.active[c]) return;
     const long long o = s.offs[c];
     const int n = (int)(s.offs[c + 1] - o);
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    const int* seg = s.seg + (size_t)c * s.nseg;
-    const int nt = (k >= seg[s.seg_trunk_lo] && k < seg[s.seg_trunk_hi]) ? s.tiles_b : s.tiles_a;
-    const A* pp = reinterpret_cast<const A*>(s.part) + s.tmax * o + k;
-    // eight independent partial sums (tiles t = j mod 8), combined in a fixed
-    // order: the loads overlap and the result does not depend on timing
-    A q[8] = {(A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0};
-    int t = 0;
-    for (; t + 8 <= nt; t += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) q[j] += pp[(size_t)(t + j) * n];
-    }
-    for (int j = 0; t < nt; ++t, ++j) q[j] += pp[(size_t)t * n];
-    const A acc = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    const int epb = 256 / sub;
+    const int kl = (int)threadIdx.x % epb, sl = (int)threadIdx.x / epb;
+    const int k = blockIdx.x * epb + kl;
+    if (sub == 1 && k >= n) return;
+    // the owning thread's state and scatter destinations, loaded before the
+    // tile sums so that their latency overlaps them
+    const bool own = k < n && sl == 0;
+    const bool drift = mode == UPD_KICK_DRIFT || mode == UPD_KICK_DRIFT_LAST;
     S* th = reinterpret_cast<S*>(s.theta) + o;
-    S x = th[k];
+    S* mo = reinterpret_cast<S*>(s.mom) + o;
+    S x = (S)0, p = (S)0;
+    int d0 = 0, d1 = 0;
+    if (own) {
+        x = th[k];
+        if (mode != UPD_GRAD) p = mo[k];
+        if (drift) {
+            d0 = s.dst[2 * (o + k)];
+            d1 = s.dst[2 * (o + k) + 1];
+        }
+    }
+    A part = (A)0;
+    if (k < n) {
+        const int* seg = s.seg + (size_t)c * s.nseg;
+        const int nt = (k >= seg[s.seg_trunk_lo] && k < seg[s.seg_trunk_hi]) ? s.tiles_b : s.tiles_a;
+        const A* pp = reinterpret_cast<const A*>(s.part) + s.tmax * o + k;
+        A q[8] = {(A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0};
+        const size_t stride = (size_t)sub * n;
+        int t = sl;
+        for (; t + 7 * sub < nt; t += 8 * sub) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q[j] += pp[(size_t)t * n + j * stride];
+        }
+        for (int j = 0; t < nt; t += sub, ++j) q[j] += pp[(size_t)t * n];
+        part = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    }
+    A acc = part;
+    if (sub > 1) {
+        red[threadIdx.x] = part;
+        __syncthreads();
+        if (sl != 0 || k >= n) return;
+        acc = red[kl];
+        for (int j = 1; j < sub; ++j) acc += red[j * epb + kl];
+    }
     const S g = (S)acc + x * (S)s.inv_prior_var;
     reinterpret_cast<S*>(s.grad)[o + k] = g;
     if (mode == UPD_GRAD) return;
     const S e = (S)s.eps[c];
-    S* mo = reinterpret_cast<S*>(s.mom) + o;
-    S p = mo[k];
     if (mode == UPD_HALF_KICK) {
         mo[k] = p - (S)0.5 * e * g;
         return;
@@ -1478,7 +1514,7 @@ __global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode) {
     const S m = s.minv ? reinterpret_cast<const S*>(s.minv)[o + k] : (S)1;
     x = x + e * m * p;
     th[k] = x;
-    scatter<P>(s, c, o + k, x, mode == UPD_KICK_DRIFT_LAST);
+    scatter_to<P>(s, c, d0, d1, x, mode == UPD_KICK_DRIFT_LAST);
 }
 
 __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0, unsigned long long k1) {
@@ -1896,8 +1932,8 @@ hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid
 #undef C_
 }
 
-hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st) {
-#define C_(p) hipLaunchKernelGGL((k_update<p>), dim3(gx, s.n_chains), dim3(256), 0, st, s, mode); return hipGetLastError()
+hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int sub, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_update<p>), dim3(gx, s.n_chains), dim3(256), 0, st, s, mode, sub); return hipGetLastError()
     HMC_DISPATCH_P(P, C_)
 #undef C_
 }

@@ -25,7 +25,7 @@ hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int
                                      const void* b0, double* mean, double* m2, double* var, double inv_k,
                                      double inv_n, hipStream_t s);
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s);
-hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
+hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int sub, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
 hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);
 hipError_t hmc_launch_momentum(int P, const StateArgs& s, hipStream_t st);
