@@ -1442,8 +1442,8 @@ __device__ __forceinline__ void scatter(const StateArgs& s, int c, long long e, 
     scatter_to<P>(s, c, s.dst[2 * e], s.dst[2 * e + 1], x, w32);
 }
 
-// Sum of the per-tile partials in tile order, plus the prior term, then the
-// kick (and drift + scatter) of the leapfrog step.  sub (a power of two, at
+// Sum of the per-tile partials, plus the prior term, then the kick (and
+// drift + scatter) of the leapfrog step.  sub (a power of two, at
 // most 8) threads per entry: thread sl of an entry sums the tiles
 // t = sl (mod sub) with eight independent partial sums (so eight loads are
 // in flight), and with sub > 1 the sub-lane sums meet in LDS and are added
