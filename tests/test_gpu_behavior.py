@@ -271,3 +271,28 @@ def test_metropolis_decisions_agree_with_fp64(prec, bound, acc_bound):
     assert 0.05 < np.mean(acc_ref) < 0.98     # the test is not vacuous
     assert d <= bound and abs(np.mean(acc) - np.mean(acc_ref)) <= acc_bound
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("L", [1, 2, 3, 6])
+@pytest.mark.parametrize("name,kw", [("uneven_mlp_bf16", dict(n_rows=150, n_chains=2)),
+                                     ("antideriv_deeponet_bf16", dict(n_u=45, n_q=17, n_chains=2))])
+def test_energy_copy_holds_the_end_positions(name, kw, L, prec):
+    """BF16 and split-BF16 engines take U in the Hamiltonian from an FP32
+    weight copy that only the first and the last drift of a trajectory
+    write.  H1 - K(p_L) must equal the U that a fresh state set to theta_L
+    gives (every copy rewritten, same energy kernels), for short trajectories
+    too (L = 1: the first drift is the last; L = 2: the last kick-drift is
+    step 1)."""
+    w = workloads.make(name, **kw)
+    s = _Sampler().from_workload(w, precision=prec)
+    p0 = np.random.default_rng(L).standard_normal(w.nnz).astype(np.float32)
+    thL, pL, H0, H1 = s.trajectory(p0, w.eps, L)
+    s.set_state(thL)
+    _, U, _ = s.get_state()
+    p = pL.double().cpu().numpy()
+    for c in range(w.n_chains):
+        K = 0.5 * float(p[w.offs[c]:w.offs[c + 1]] @ p[w.offs[c]:w.offs[c + 1]])
+        print(f"{name} {prec} L={L} chain {c}: H1 {H1[c]:.12e}, U(theta_L) + K {U[c] + K:.12e}")
+        assert abs(H1[c] - (U[c] + K)) <= 1e-12 * abs(H1[c])
+    s.close()
