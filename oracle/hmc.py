@@ -104,3 +104,73 @@ def sample_chain(potential_and_grad, theta_init, eps, L, n, seed, chain,
         out[i] = theta
         stats.append(st)
     return out, stats
+
+
+# ---------------------------------------------------------------------------
+# Step-size adaptation (Sec. 4.3: step sizes for an 80% acceptance rate by
+# the dual-averaging scheme of Hoffman and Gelman, 2014) and the trajectory
+# length rule of App. C.
+
+DA_GAMMA, DA_T0, DA_KAPPA = 0.05, 10.0, 0.75
+
+
+def dual_averaging_start(eps0):
+    """State of the dual-averaging iteration before the first trajectory:
+    no iterations yet, H-bar = 0, log eps-bar = 0, and the shrinkage point
+    mu = log(10 eps0)."""
+    return {"m": 0, "hbar": 0.0, "log_bar": 0.0, "mu": math.log(10.0 * eps0)}
+
+
+def dual_averaging_update(state, alpha, target=0.8, gamma=DA_GAMMA, t0=DA_T0, kappa=DA_KAPPA):
+    """One update after a trajectory whose acceptance statistic is alpha.
+    The iteration drives the running average H-bar of (target - alpha) to
+    zero: H-bar_m is the (m + t0)-weighted mean of the deviations, the next
+    log step size sits sqrt(m)/gamma * H-bar_m below mu, and the returned
+    averaged log step size weighs iterate m by m^-kappa.  Returns the step
+    size of the next trajectory (the averaged one is state["log_bar"])."""
+    m = state["m"] + 1
+    w = 1.0 / (m + t0)
+    hbar = (1.0 - w) * state["hbar"] + w * (target - alpha)
+    log_eps = state["mu"] - math.sqrt(m) / gamma * hbar
+    eta = m ** (-kappa)
+    state.update(m=m, hbar=hbar, log_bar=eta * log_eps + (1.0 - eta) * state["log_bar"])
+    return math.exp(log_eps)
+
+
+def acceptance_probability(H0, H1) -> float:
+    """Metropolis acceptance probability min(1, exp(H0 - H1)); 0 for a
+    non-finite H1 (a divergent trajectory)."""
+    if not math.isfinite(H1):
+        return 0.0
+    return min(1.0, math.exp(min(H0 - H1, 0.0)))
+
+
+def adapt_chain(potential_and_grad, theta_init, eps0, L, n, seed, chain, target=0.8,
+                inv_mass=None, start_iter=0):
+    """n iterations of Algorithm 2 for one chain (the Philox streams of
+    sample_chain) whose step size is updated by dual averaging after every
+    Metropolis step.  Returns (averaged step size eps-bar, final theta, the
+    step sizes used, list of stats)."""
+    theta = np.array(theta_init, dtype=np.float64)
+    U, g = potential_and_grad(theta)
+    st_da = dual_averaging_start(eps0)
+    eps, used, stats = eps0, [], []
+    for i in range(n):
+        it = start_iter + i
+        p = momentum(seed, chain, it, theta.size, inv_mass)
+        u = philox.metropolis_uniform(seed, chain, it)
+        used.append(eps)
+        theta, U, g, st = transition(potential_and_grad, theta, U, g, p, eps, L, u, inv_mass)
+        stats.append(st)
+        eps = dual_averaging_update(st_da, acceptance_probability(st["H0"], st["H1"]), target)
+    return math.exp(st_da["log_bar"]), theta, used, stats
+
+
+def trajectory_length(var, eps, mode="median") -> int:
+    """Number of leapfrog steps of App. C: pi times the posterior variance
+    over twice the step size, rounded to the nearest integer (at least one).
+    The posterior variance is the largest ("max") or the median ("median")
+    of the given per-parameter variances."""
+    v = np.asarray(var, dtype=np.float64).ravel()
+    pv = float(v.max()) if mode == "max" else float(np.median(v))
+    return max(1, int(round(math.pi * pv / (2.0 * eps))))

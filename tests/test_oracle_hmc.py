@@ -208,3 +208,94 @@ def test_sampler_recovers_one_dimensional_nonlinear_conditional():
     ess = _ess_1d(s)
     assert abs(s.mean() - mean) < 5 * math.sqrt(var / ess), (s.mean(), mean)
     assert abs(s.var() - var) < 0.15 * var
+
+
+# ---------------------------------------------------------------------------
+# Step-size adaptation (dual averaging) and the App. C trajectory length.
+
+def test_dual_averaging_fixed_point():
+    """When every trajectory accepts with exactly the target probability the
+    running deviation stays zero, every step size equals exp(mu) = 10 eps0,
+    and so does the average."""
+    st = oh.dual_averaging_start(3e-4)
+    for _ in range(50):
+        e = oh.dual_averaging_update(st, 0.8, target=0.8)
+        assert math.isclose(e, 3e-3, rel_tol=1e-12)
+    assert math.isclose(math.exp(st["log_bar"]), 3e-3, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("target", [0.65, 0.8, 0.9])
+def test_dual_averaging_solves_a_known_acceptance_curve(target):
+    """With a deterministic acceptance curve alpha(eps) = exp(-(eps/s)^2) the
+    averaged step size must converge to the root s sqrt(-ln target), from
+    either side (a sign or scale mistake in the update drifts away)."""
+    s = 2e-3
+    root = s * math.sqrt(-math.log(target))
+    for eps0 in (1e-5, 5e-2):
+        st = oh.dual_averaging_start(eps0)
+        e = eps0
+        for _ in range(20000):
+            e = oh.dual_averaging_update(st, math.exp(-(e / s) ** 2), target=target)
+        assert abs(math.exp(st["log_bar"]) / root - 1.0) < 0.01
+
+
+def test_acceptance_probability():
+    assert oh.acceptance_probability(1.0, 0.5) == 1.0
+    assert math.isclose(oh.acceptance_probability(0.5, 1.0), math.exp(-0.5), rel_tol=1e-15)
+    assert oh.acceptance_probability(0.0, math.inf) == 0.0
+    assert oh.acceptance_probability(0.0, math.nan) == 0.0
+
+
+def test_adapted_step_size_gives_the_target_acceptance_on_a_gaussian():
+    """Adaptation on a 12-dimensional Gaussian with precisions from 1 to 400
+    (L = 12), then the expected acceptance at the adapted step size computed
+    without the sampler: per dimension the leapfrog is the linear map of one
+    step raised to the power L (a matrix power), applied to exact draws of
+    the stationary distribution, with H evaluated in closed form."""
+    lam = np.geomspace(1.0, 400.0, 12)
+    pg = lambda th: (0.5 * float(th @ (lam * th)), lam * th)
+    L = 12
+    eps_bar, _, used, _ = oh.adapt_chain(pg, np.zeros(12), 1e-3, L, 1500, seed=5, chain=0, target=0.8)
+    assert used[0] == 1e-3 and eps_bar > 1e-3
+    rng = np.random.default_rng(0)
+    n = 200000
+    th = rng.standard_normal((n, 12)) / np.sqrt(lam)
+    p = rng.standard_normal((n, 12))
+    H0 = 0.5 * (lam * th * th).sum(1) + 0.5 * (p * p).sum(1)
+    th1, p1 = np.empty_like(th), np.empty_like(p)
+    for i, l in enumerate(lam):
+        kick = np.array([[1.0, 0.0], [-0.5 * eps_bar * l, 1.0]])      # (theta, p) -> (theta, p - eps/2 l theta)
+        drift = np.array([[1.0, eps_bar], [0.0, 1.0]])
+        M = np.linalg.matrix_power(kick @ drift @ kick, L)
+        th1[:, i], p1[:, i] = M[0, 0] * th[:, i] + M[0, 1] * p[:, i], M[1, 0] * th[:, i] + M[1, 1] * p[:, i]
+    H1 = 0.5 * (lam * th1 * th1).sum(1) + 0.5 * (p1 * p1).sum(1)
+    acc = np.minimum(1.0, np.exp(np.minimum(H0 - H1, 0.0))).mean()
+    assert abs(acc - 0.8) < 0.03, (eps_bar, acc)
+
+
+def test_trajectory_length_is_a_quarter_period_on_a_unit_gaussian():
+    """For a standard normal target the exact flow over time pi/2 turns
+    (theta, p) into (p, -theta); the rule at unit variance picks that time,
+    so the leapfrog end point is the quarter turn up to O(eps^2)."""
+    for eps in (0.05, 0.01):
+        L = oh.trajectory_length([1.0], eps)
+        assert abs(L * eps - math.pi / 2) <= eps / 2
+        th, p, _, _ = oh.leapfrog(lambda t: (0.5 * float(t @ t), t), np.array([0.7, -1.2]), np.array([0.3, 0.9]),
+                                  eps, L)
+        assert np.abs(th - np.array([0.3, 0.9])).max() < 2 * eps
+        assert np.abs(p - np.array([-0.7, 1.2])).max() < 2 * eps
+
+
+def test_trajectory_length_of_the_app_c_cases():
+    """The App. C table prints the posterior variance and the VI-HMC step
+    size of each case; the rule gives the step counts in the fixture (the
+    paper prints the rule, not the counts).  Median and largest variance."""
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "appc_trajectory_lengths.json")))
+    for case in d["cases"]:
+        assert oh.trajectory_length([case["posterior_variance"]], case["step_size"]) == case["L"], case
+    v = [0.1, 0.4, 0.2, 0.3]
+    assert oh.trajectory_length(v, 0.01, "max") == round(math.pi * 0.4 / 0.02)
+    assert oh.trajectory_length(v, 0.01, "median") == round(math.pi * 0.25 / 0.02)
+    assert oh.trajectory_length([1e-9], 1.0) == 1
