@@ -145,16 +145,43 @@ def acceptance_probability(H0, H1) -> float:
     return min(1.0, math.exp(min(H0 - H1, 0.0)))
 
 
+def reasonable_step_size(potential_and_grad, theta, p, eps, inv_mass=None, max_probes=60):
+    """Starting step size of the adaptation (the heuristic Hoffman and Gelman
+    start dual averaging from): the acceptance ratio exp(H0 - H1) of one
+    leapfrog step from (theta, p) decides a direction, up if it exceeds 1/2,
+    down otherwise; the step size then doubles (or halves) as long as the
+    ratio stays on that side, and the first step size where it crosses is
+    returned.  A non-finite H1 counts as ratio 0."""
+    U, g = potential_and_grad(np.asarray(theta, dtype=np.float64))
+    H0 = hamiltonian(U, p, inv_mass)
+
+    def above(e):
+        _, p1, U1, _ = leapfrog(potential_and_grad, theta, p, e, 1, inv_mass, start=(U, g))
+        H1 = hamiltonian(U1, p1, inv_mass)
+        return math.isfinite(H1) and H0 - H1 > -math.log(2.0)
+
+    up = above(eps)
+    for _ in range(max_probes):
+        e = 2.0 * eps if up else 0.5 * eps
+        eps = e
+        if above(e) != up:
+            break
+    return eps
+
+
 def adapt_chain(potential_and_grad, theta_init, eps0, L, n, seed, chain, target=0.8,
                 inv_mass=None, start_iter=0):
     """n iterations of Algorithm 2 for one chain (the Philox streams of
     sample_chain) whose step size is updated by dual averaging after every
-    Metropolis step.  Returns (averaged step size eps-bar, final theta, the
-    step sizes used, list of stats)."""
+    Metropolis step, starting from the reasonable step size found from eps0
+    with the momentum of the first iteration.  Returns (averaged step size
+    eps-bar, final theta, the step sizes used, list of stats)."""
     theta = np.array(theta_init, dtype=np.float64)
     U, g = potential_and_grad(theta)
-    st_da = dual_averaging_start(eps0)
-    eps, used, stats = eps0, [], []
+    eps1 = reasonable_step_size(potential_and_grad, theta,
+                                momentum(seed, chain, start_iter, theta.size, inv_mass), eps0, inv_mass)
+    st_da = dual_averaging_start(eps1)
+    eps, used, stats = eps1, [], []
     for i in range(n):
         it = start_iter + i
         p = momentum(seed, chain, it, theta.size, inv_mass)

@@ -256,7 +256,7 @@ def test_adapted_step_size_gives_the_target_acceptance_on_a_gaussian():
     pg = lambda th: (0.5 * float(th @ (lam * th)), lam * th)
     L = 12
     eps_bar, _, used, _ = oh.adapt_chain(pg, np.zeros(12), 1e-3, L, 1500, seed=5, chain=0, target=0.8)
-    assert used[0] == 1e-3 and eps_bar > 1e-3
+    assert used[0] > 1e-3 and math.log2(used[0] / 1e-3) % 1 == 0   # moved by the starting heuristic
     rng = np.random.default_rng(0)
     n = 200000
     th = rng.standard_normal((n, 12)) / np.sqrt(lam)
@@ -299,3 +299,23 @@ def test_trajectory_length_of_the_app_c_cases():
     assert oh.trajectory_length(v, 0.01, "max") == round(math.pi * 0.4 / 0.02)
     assert oh.trajectory_length(v, 0.01, "median") == round(math.pi * 0.25 / 0.02)
     assert oh.trajectory_length([1e-9], 1.0) == 1
+
+
+@pytest.mark.parametrize("th0,p0,eps0", [(0.7, -0.3, 1e-6), (1.5, 0.9, 40.0), (-0.2, 2.0, 0.8), (0.0, 0.1, 3.0)])
+def test_reasonable_step_size_stops_where_one_step_crosses_one_half(th0, p0, eps0):
+    """On a unit Gaussian one kick-drift-kick step changes the energy by
+    exactly (e^2/8)(theta_1^2 - theta_0^2), theta_1 = theta_0 (1 - e^2/2) + e p_0
+    (the conserved shadow energy).  The heuristic must return eps0 times a
+    power of two at which that ratio has crossed 1/2, having stayed on the
+    starting side at the step before."""
+    def ratio(e):
+        t1 = th0 * (1 - e * e / 2) + e * p0
+        return math.exp(-(e * e / 8) * (t1 * t1 - th0 * th0))
+    pg = lambda t: (0.5 * float(t @ t), t.copy())
+    e = oh.reasonable_step_size(pg, np.array([th0]), np.array([p0]), eps0)
+    k = math.log2(e / eps0)
+    assert abs(k - round(k)) < 1e-12 and round(k) != 0
+    up = ratio(eps0) > 0.5
+    prev = e / 2 if up else e * 2
+    assert (ratio(prev) > 0.5) == up
+    assert (ratio(e) > 0.5) != up
