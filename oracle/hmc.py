@@ -201,3 +201,34 @@ def trajectory_length(var, eps, mode="median") -> int:
     v = np.asarray(var, dtype=np.float64).ravel()
     pv = float(v.max()) if mode == "max" else float(np.median(v))
     return max(1, int(round(math.pi * pv / (2.0 * eps))))
+
+
+def calibrate_chain(potential_and_grad, theta_init, eps0, L, rounds, batch, seed, chain, target=0.8,
+                    inv_mass=None, start_iter=0):
+    """Bisection of one chain's step size in log eps on the batch mean of
+    the acceptance probability: each round runs `batch` iterations of
+    Algorithm 2 at the current step size; a mean above the target makes it
+    a lower bound, otherwise an upper bound, and the next step size is the
+    midpoint of the bounds in log eps (a factor 1.25 up or down while one
+    bound is missing).  Returns (final midpoint, last batch mean, theta)."""
+    theta = np.array(theta_init, dtype=np.float64)
+    U, g = potential_and_grad(theta)
+    lo, hi, lx, it, mean = -math.inf, math.inf, math.log(eps0), start_iter, 0.0
+    for _ in range(rounds):
+        eps, s = math.exp(lx), 0.0
+        for _ in range(batch):
+            p = momentum(seed, chain, it, theta.size, inv_mass)
+            u = philox.metropolis_uniform(seed, chain, it)
+            theta, U, g, st = transition(potential_and_grad, theta, U, g, p, eps, L, u, inv_mass)
+            s += acceptance_probability(st["H0"], st["H1"])
+            it += 1
+        mean = s / batch
+        if mean > target:
+            lo = lx
+        else:
+            hi = lx
+        if math.isfinite(lo) and math.isfinite(hi):
+            lx = 0.5 * (lo + hi)
+        else:
+            lx += math.log(1.25) if math.isfinite(lo) else -math.log(1.25)
+    return math.exp(lx), mean, theta

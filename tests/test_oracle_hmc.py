@@ -319,3 +319,19 @@ def test_reasonable_step_size_stops_where_one_step_crosses_one_half(th0, p0, eps
     prev = e / 2 if up else e * 2
     assert (ratio(prev) > 0.5) == up
     assert (ratio(e) > 0.5) != up
+
+
+def test_calibration_brackets_the_step_size_of_the_target_acceptance():
+    """Bisection on batch means for a one-dimensional Gaussian and L = 1,
+    where the expected acceptance at step size e has a closed form over the
+    stationary draws (the one-step energy change is (e^2/8)(theta_1^2 -
+    theta_0^2)): after enough rounds of large batches the expected
+    acceptance at the returned step size is the target to 0.02."""
+    def expected(e, n=400000):
+        r = np.random.default_rng(1)
+        th, p = r.standard_normal(n), r.standard_normal(n)
+        t1 = th * (1 - e * e / 2) + e * p
+        return np.minimum(1.0, np.exp(-(e * e / 8) * (t1 * t1 - th * th))).mean()
+    pg = lambda t: (0.5 * float(t @ t), t.copy())
+    e, mean, _ = oh.calibrate_chain(pg, np.array([0.3]), 1.0, 1, rounds=9, batch=1500, seed=3, chain=0, target=0.8)
+    assert abs(expected(e) - 0.8) < 0.02, (e, expected(e), mean)
