@@ -6,10 +6,12 @@ weight gradient), Hamiltonian and Metropolis test, and the copy of the new
 positions into a device-resident sample buffer.  The metric is leapfrog
 gradient evaluations per second summed over chains.
 
-Prints one JSON line.  The default workload is the FP32 MLP regression
-(2-64-64-64-1 tanh, 4096 rows, 10% of the parameters sampled, 8 chains,
-L = 50, per-chain step sizes adapted from 5e-4 to 80% acceptance before the
-timed region); --config selects another named workload.
+Prints one JSON line.  The default workload is the largest single-GPU
+configuration, the batched uneven chains: 256 chains on the MLP
+4-256-256-256-256-1 tanh over 16,384 rows, each chain sampling its own 1% to
+20% of the parameters, BF16 products, L = 50, per-chain step sizes adapted
+on the device to 80% acceptance before the timed region; --config selects
+another named workload.
 """
 
 from __future__ import annotations
@@ -317,29 +319,63 @@ def predict_bench(config, n_samples, n_new, cpu_budget):
     print(json.dumps(line))
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on the host cores: gradient evaluations per second,
-    summed over the chains it ran, on a bounded sample of the workload."""
-    from threadpoolctl import threadpool_info
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def _oracle_grad_rate(w, budget_s):
+    """Leapfrog gradient evaluations of the FP64 oracle along trajectories
+    that cycle over the workload's chains, each evaluation timed as it runs
+    and the loop stopped at the budget (large workloads finish only part of
+    a trajectory).  Returns (evaluations/s, evaluations, seconds)."""
     from oracle import hmc as oh
     from oracle import network as on
 
-    evals, trajs, t0 = 0, 0, time.perf_counter()
+    evals, t0, traj = 0, time.perf_counter(), 0
     while time.perf_counter() - t0 < budget_s:
-        c = trajs % w.n_chains
+        c = traj % w.n_chains
         post = on.posterior_for_chain(w, c)
         th = w.chain_theta(c)
-        p = oh.momentum(1, c, trajs // w.n_chains, th.size)
-        start = post.potential_and_grad(th)
-        oh.leapfrog(post.potential_and_grad, th, p, w.eps, w.L, start=start)
-        evals += w.L + 1
-        trajs += 1
+        p = oh.momentum(1, c, traj // w.n_chains, th.size)
+        U, g = post.potential_and_grad(th)
+        evals += 1
+        p = p - 0.5 * w.eps * g
+        for t in range(1, w.L + 1):
+            if time.perf_counter() - t0 >= budget_s:
+                break
+            th = th + w.eps * p
+            U, g = post.potential_and_grad(th)
+            evals += 1
+            p = p - (w.eps if t < w.L else 0.5 * w.eps) * g
+        traj += 1
     dt = time.perf_counter() - t0
+    return evals / dt, evals, dt
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle on the host cores, gradient evaluations per second on
+    a bounded sample of the workload: once with every core BLAS offers and
+    once on one thread (half the budget each).  value / cores: the all-core
+    run and the threads it used."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    half = 0.5 * budget_s
+    v_all, n_all, t_all = _oracle_grad_rate(w, half)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": evals / dt, "unit": "grad-evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{trajs} trajectories of L={w.L} (+1 start evaluation each) cycling over the "
-                      f"{w.n_chains} chains of the same workload, FP64 NumPy, {dt:.1f} s"}
+    with threadpool_limits(limits=1):
+        v_one, n_one, t_one = _oracle_grad_rate(w, half)
+    return {"value": v_all, "unit": "grad-evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_all} leapfrog gradient evaluations (trajectories of L={w.L} cycling over the "
+                      f"{w.n_chains} chains, stopped at the budget), FP64 NumPy, {t_all:.1f} s",
+            "single_thread": {"value": v_one, "unit": "grad-evals/s", "cores": 1,
+                              "sample": f"{n_one} gradient evaluations, {t_one:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 # ---------------------------------------------------------------------------
@@ -451,7 +487,6 @@ def ess_comparison(w, seed, budget_s=20.0):
     uses chain 0's step size."""
     import torch
     from paper_2507_14652_amd import Sampler
-    from paper_2507_14652_amd.warmup import adapt_step_size
     s = Sampler.from_workload(w, seed=seed)
     C, L = w.n_chains, w.L
     th = s.get_state()[0].double().cpu().numpy()
@@ -465,7 +500,7 @@ def ess_comparison(w, seed, budget_s=20.0):
         v = b2 * v + (1 - b2) * g * g
         th = th - lr * (m / (1 - b1 ** k)) / (np.sqrt(v / (1 - b2 ** k)) + 1e-8)
     s.set_state(th.astype(np.float32))
-    eps_c = adapt_step_size(s, w.eps, L, n_adapt=300)
+    eps_c = s.adapt(300, w.eps, L)
     s.sample(50, eps_c, L)
     n = 400
     out = torch.empty((n, w.nnz), dtype=torch.float32, device="cuda")
@@ -474,11 +509,16 @@ def ess_comparison(w, seed, budget_s=20.0):
     _, st = s.sample(n, eps_c, L, out=out)
     torch.cuda.synchronize()
     t_eng = time.perf_counter() - t0
-    ns = w.nnz // C
-    draws = out.cpu().numpy().reshape(n, C, ns)
-    ess_eng = bulk_ess(draws)
+    flat = out.cpu().numpy()
+    sizes = np.diff(w.offs)
+    if np.all(sizes == sizes[0]) and all(np.array_equal(w.chain_idx(c), w.chain_idx(0)) for c in range(C)):
+        # one subset for every chain: the chains' draws of each coordinate combine
+        ess_eng = bulk_ess(flat.reshape(n, C, sizes[0]))
+    else:
+        # masks differ per chain: each chain's coordinates are its own
+        ess_eng = np.concatenate([bulk_ess(flat[:, None, w.offs[c]:w.offs[c + 1]]) for c in range(C)])
     acc_eng = float(st["accepted"].mean())
-    start0 = draws[-1, 0]
+    start0 = flat[-1, w.offs[0]:w.offs[1]]
     eps = float(eps_c[0])
     base, acc_base, t_base = plain_torch_hmc(w, start0, eps, L, n, seed + 1, budget_s)
     ess_base = bulk_ess(base[:, None, :])
@@ -503,13 +543,13 @@ def ess_comparison(w, seed, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="regress2d_fp32")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="uneven_mlp_bf16")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-reps", type=int, default=50)
-    ap.add_argument("--adapt", type=int, default=150,
+    ap.add_argument("--adapt", type=int, default=40,
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--precision", choices=("fp64", "fp32", "bf16", "bf16x3"),
                     help="run --config's workload at another precision (a comparison, not the headline line)")
@@ -541,7 +581,7 @@ def main():
         predict_bench(args.config, 200, 4096, 0.0 if args.no_cpu_baseline else 10.0)
         return
     if args.sensitivity:
-        sensitivity_bench(args.config, args.steps if args.steps != 200 else 5, 0.0 if args.no_cpu_baseline else 10.0)
+        sensitivity_bench(args.config, args.steps if args.steps != 20 else 5, 0.0 if args.no_cpu_baseline else 10.0)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); chains are independent and would "
@@ -552,7 +592,6 @@ def main():
 
     import workloads
     from paper_2507_14652_amd import Sampler, autotune_workload
-    from paper_2507_14652_amd.warmup import adapt_step_size
 
     w = workloads.make(args.config)
     if args.precision:
@@ -565,7 +604,7 @@ def main():
     warm = torch.empty((max(args.warmup, 1), w.nnz), dtype=st_dtype, device="cuda")
     # untimed: per-chain step sizes by dual averaging to 80% acceptance, then
     # the warm-up iterations at those step sizes
-    eps_c = adapt_step_size(s, w.eps, L, n_adapt=args.adapt) if args.adapt else np.full(C, w.eps)
+    eps_c = s.adapt(args.adapt, w.eps, L) if args.adapt else np.full(C, w.eps)
     if args.warmup:
         s.sample(args.warmup, eps_c, L, out=warm)
     torch.cuda.synchronize()

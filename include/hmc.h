@@ -69,6 +69,18 @@ typedef enum {
  * BF16X3 engines come from a float forward pass. */
 typedef enum { HMC_FP64 = 0, HMC_FP32 = 1, HMC_BF16 = 2, HMC_BF16X3 = 3 } hmc_precision;
 
+/* Where U of the Hamiltonian (H0, H1, the Metropolis test) comes from.
+ * DEFAULT: FP64 sums over the engine's own float products (FP32 engines),
+ * or over a separate forward pass with float products on a float copy of
+ * the weights (BF16 and BF16X3 engines); FP64 engines use their own FP64
+ * pass.  FP64: a separate forward pass entirely in FP64 (FP64 copies of
+ * the weights, biases and inputs, FP64 matrix cores) for FP32, BF16 and
+ * BF16X3 engines, once per trajectory.  Acceptance depends on energy
+ * differences of order one (Sec. 2.2); when U itself is very large (many
+ * outputs with a small likelihood sd) the relative error of a float forward
+ * pass, about 1e-7 of U, exceeds them. */
+typedef enum { HMC_ENERGY_DEFAULT = 0, HMC_ENERGY_FP64 = 1 } hmc_energy;
+
 /* Network family (Sec. 2 and App. A).  An MLP is one fully connected tower;
  * a DeepONet has a branch tower over input-function samples and a trunk
  * tower over query coordinates, combined by a dot product plus a scalar
@@ -85,6 +97,7 @@ typedef enum { HMC_MLP = 0, HMC_DEEPONET = 1 } hmc_net_kind;
  *   unless hmc_mask_desc.theta_init is given.
  * inv_mass_diag: NULL for M = I, else n_params positive diagonal entries of
  *   M^-1 (only the selected ones are used).
+ * energy: hmc_energy (HMC_ENERGY_DEFAULT or HMC_ENERGY_FP64).
  * Limits: 2..9 widths per tower, each width 1..4096. */
 typedef struct {
     int32_t kind;
@@ -98,6 +111,7 @@ typedef struct {
     double lik_sd;
     int32_t precision;
     const double* inv_mass_diag;
+    int32_t energy;
 } hmc_net_desc;
 
 /* The selected subset Theta_s of each chain (Sec. 3.2), as CSR over chains.
@@ -149,10 +163,14 @@ typedef struct {
     int64_t device_bytes;     /* device memory held by the engine            */
     int32_t threads_a;        /* threads per workgroup of the MLP / branch   */
     int32_t threads_b;        /* ... and of the trunk tile kernels           */
+    int32_t energy_precision; /* hmc_precision of the forward pass behind U  */
 } hmc_info_t;
 
-/* Creates an engine: validates, uploads data and parameters, and evaluates
- * U and its gradient at the starting point of every chain.
+/* Creates an engine for the sampling problem of Algorithm 2 (Sec. 3.2: the
+ * network F_Theta, the fixed values mu_~s, the subset s, the Gaussian prior
+ * and likelihood of App. C, the data D and a starting Theta_s per chain):
+ * validates, uploads data and parameters, and evaluates U and its gradient
+ * at the starting point of every chain.
  * seed keys the Philox4x64-10 streams of the momentum refresh and of the
  * Metropolis uniforms (key = (seed, chain), counter = (iteration, stream,
  * block, 0)).  hip_stream: a hipStream_t to queue work on, or NULL for a
@@ -190,7 +208,7 @@ hmc_status hmc_init_tuned(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask
 hmc_status hmc_autotune(const hmc_net_desc* net, const hmc_mask_desc* mask, const hmc_data_desc* data,
                         int32_t reps, hmc_tuning* best, double* best_ms);
 
-/* One iteration of the loop of Algorithm 2 for the listed chains: draw
+/* One iteration of the loop of Algorithm 2 (Sec. 3.2) for the listed chains: draw
  * p ~ N(0, M), integrate L leapfrog steps of size eps[i] for chain
  * chain_ids[i] (kick-drift-kick, exactly L gradient evaluations), then
  * accept or reject.  chain_ids NULL means chains 0..n_chains-1.
@@ -207,23 +225,29 @@ hmc_status hmc_sample(hmc_ctx* ctx, int64_t n, const double* eps, int32_t L,
                       void* samples, hmc_traj_stat* stats);
 
 /* U (host, [C]) and the gradient of U with respect to the selected entries
- * (state type, host or device, [nnz]) at the current positions. */
+ * (state type, host or device, [nnz]) at the current positions: the
+ * potential of Sec. 2.2 with the prior and likelihood of App. C, and the
+ * gradient that each leapfrog step of Algorithm 2 takes, for every chain. */
 hmc_status hmc_grad(hmc_ctx* ctx, double* U, void* g);
 
-/* A trajectory without Metropolis step and without changing the engine
- * state: starting from the current positions with momentum p0 (state type,
+/* The leapfrog integration of Hamilton's equations (Sec. 2.2) that one
+ * iteration of Algorithm 2 runs, for every chain, without the Metropolis
+ * step and without changing the engine state: starting from the current
+ * positions with momentum p0 (state type,
  * host or device, [nnz]), run L leapfrog steps of size eps[c] (host, [C]) and
  * return the end point theta_out, p_out ([nnz], host or device, may be NULL)
  * and H0, H1 (host, [C], may be NULL). */
 hmc_status hmc_trajectory(hmc_ctx* ctx, const void* p0, const double* eps, int32_t L,
                           void* theta_out, void* p_out, double* H0, double* H1);
 
-/* The momentum that the refresh of iteration `iteration` draws, for every
- * chain (state type, host or device, [nnz]). */
+/* The momentum p ~ N(0, M) that the refresh of Algorithm 2 draws at
+ * iteration `iteration`, for every chain (state type, host or device,
+ * [nnz]).  The engine state is unchanged. */
 hmc_status hmc_momentum(hmc_ctx* ctx, uint64_t iteration, void* p_out);
 
-/* Current positions (state type, host or device, [nnz], may be NULL), U
- * (host [C] or NULL) and per-chain iteration counters (host [C] or NULL). */
+/* The chain state of Algorithm 2: current positions (state type, host or
+ * device, [nnz], may be NULL), U (host [C] or NULL) and per-chain iteration
+ * counters (host [C] or NULL). */
 hmc_status hmc_get_state(hmc_ctx* ctx, void* theta_s, double* U, uint64_t* iteration);
 
 /* Sets the positions (state type, host or device, [nnz]) and iteration
@@ -233,7 +257,8 @@ hmc_status hmc_get_state(hmc_ctx* ctx, void* theta_s, double* U, uint64_t* itera
 hmc_status hmc_set_state(hmc_ctx* ctx, const void* theta_s, const uint64_t* iteration);
 
 /* Accepted and divergent trajectory counts per chain since hmc_init (host,
- * [C] each, either may be NULL). */
+ * [C] each, either may be NULL): the outcomes of the Metropolis step of
+ * Algorithm 2 (a divergent trajectory, Sec. 4.3, is a rejection). */
 hmc_status hmc_counters(hmc_ctx* ctx, int64_t* accepted, int64_t* divergent);
 
 hmc_status hmc_get_info(const hmc_ctx* ctx, hmc_info_t* info);
@@ -295,6 +320,47 @@ hmc_status hmc_predict(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t
  * idx: host [n], receives the N selected indices in increasing order (a
  * mask for hmc_init); *n_sel = N (it may be 0).  Host only. */
 hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel);
+
+/* Step-size adaptation for a target acceptance rate (Sec. 4.3 fixes it at
+ * 80% with the dual-averaging scheme of Hoffman and Gelman, 2014): runs n
+ * iterations of Algorithm 2 for every chain (they move the chains and
+ * advance the iteration counters; nothing is stored), each chain starting
+ * at eps0[c] (host, [C], positive finite) and updating its own step size on
+ * the device after every Metropolis step from the trajectory's acceptance
+ * probability min(1, exp(H0 - H1)) (0 if divergent), with gamma = 0.05,
+ * t0 = 10, kappa = 0.75, mu = log(10 eps0[c]).  eps_out (host, [C]): the
+ * averaged iterate eps-bar of each chain, the step size to sample with.
+ * L >= 1 is the common trajectory length; target in (0, 1).  Synchronous.
+ * Errors: HMC_EINVAL (state unchanged), HMC_EDEVICE. */
+hmc_status hmc_adapt(hmc_ctx* ctx, int64_t n, const double* eps0, int32_t L, double target, double* eps_out);
+
+/* Step sizes for a target acceptance rate to within the noise of a batch
+ * mean (the matched 80% acceptance of Sec. 4.3's comparison; dual
+ * averaging alone settles somewhat above its target): per chain, a
+ * bisection in log eps over `rounds` rounds of `batch` iterations of
+ * Algorithm 2 each (they move the chains; nothing is stored).  Each round
+ * runs at the current step sizes and sums every trajectory's acceptance
+ * probability min(1, exp(H0 - H1)) (0 if divergent) on the device; a chain
+ * whose batch mean exceeds the target takes its step size as a lower bound,
+ * otherwise as an upper bound, and moves to the midpoint of its bounds in log
+ * eps (by a factor 1.25 while one bound is missing).  eps_in (host, [C]):
+ * the starting step sizes (e.g. from hmc_adapt); eps_out (host, [C]): the
+ * final midpoints; acc_out (host, [C], or NULL): each chain's batch mean in
+ * the last round.  rounds in 1..64, batch >= 1, L >= 1, target in (0, 1).
+ * Synchronous.  Errors: HMC_EINVAL (state unchanged), HMC_EDEVICE. */
+hmc_status hmc_calibrate(hmc_ctx* ctx, int32_t rounds, int64_t batch, const double* eps_in, int32_t L, double target,
+                         double* eps_out, double* acc_out);
+
+/* Number of leapfrog steps from App. C: L = pi * v / (2 eps), rounded to the
+ * nearest integer and at least 1, where v is the largest (mode 0) or the
+ * median (mode 1) of the n posterior variances var (host, finite, >= 0;
+ * App. C takes the largest VI variance for Burgers and BNN case I and the
+ * median elsewhere).  The product L * eps is then a fixed integration time
+ * pi * v / 2, as in the fixed simulation length of Hoffman and Gelman's HMC
+ * with dual averaging.  Host only.  Errors: HMC_EINVAL (NULL pointers,
+ * n < 1, bad mode, eps not positive and finite, a variance not finite or
+ * negative, more than 10^6 steps); the message is in hmc_last_error(NULL). */
+hmc_status hmc_trajectory_length(const double* var, int64_t n, int32_t mode, double eps, int32_t* L);
 
 /* Waits for queued work and reports deferred device errors. */
 hmc_status hmc_sync(hmc_ctx* ctx);

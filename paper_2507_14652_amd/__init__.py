@@ -8,4 +8,4 @@ arguments to it.
 """
 
 from .binding import (HMCError, STAT_DTYPE, Sampler, autotune, autotune_workload, load,  # noqa: F401
-                      select_mask, sensitivities)
+                      select_mask, sensitivities, trajectory_length)

@@ -16,7 +16,15 @@ class MaskedPotential(torch.autograd.Function):
     """forward(theta_s [nnz], sampler) -> U [n_chains] (float64): sets the
     engine's positions to theta_s (so the engine state changes, as
     Sampler.set_state does) and returns the potential of every chain.
-    backward: grad_out[c] * dU_c/dtheta_s over chain c's entries."""
+    backward: grad_out[c] * dU_c/dtheta_s over chain c's entries.
+
+    FP64 and FP32 engines: backward is the derivative of forward (the same
+    products).  BF16 and split-BF16 engines: forward returns U from their
+    FP32 energy pass and backward the gradient of their BF16 products, the
+    quantities the leapfrog and the Metropolis test of those engines use; so
+    backward equals the derivative of forward only up to the gradient error
+    of the BF16 products (about 1e-2 relative for BF16, 1e-5 for split
+    BF16)."""
 
     @staticmethod
     def forward(ctx, theta_s, sampler):

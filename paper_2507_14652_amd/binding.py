@@ -20,13 +20,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmc.so")
 
 HMC_OK, HMC_EINVAL, HMC_ENOMEM, HMC_EDEVICE, HMC_ESTATE, HMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+ENERGY = {"default": 0, "fp64": 1}
 KIND = {"mlp": 0, "deeponet": 1}
 
 ABI_FUNCTIONS = (
     "hmc_init", "hmc_leapfrog", "hmc_sample", "hmc_grad", "hmc_trajectory", "hmc_momentum",
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
     "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
-    "hmc_predict", "hmc_init_tuned", "hmc_autotune",
+    "hmc_predict", "hmc_init_tuned", "hmc_autotune", "hmc_adapt", "hmc_trajectory_length",
+    "hmc_calibrate",
 )
 
 
@@ -40,7 +42,7 @@ class NetDesc(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("n_widths_a", c_int32), ("widths_a", POINTER(c_int32)),
                 ("n_widths_b", c_int32), ("widths_b", POINTER(c_int32)), ("theta0", POINTER(c_double)),
                 ("n_params", c_int64), ("prior_sd", c_double), ("lik_sd", c_double),
-                ("precision", c_int32), ("inv_mass_diag", POINTER(c_double))]
+                ("precision", c_int32), ("inv_mass_diag", POINTER(c_double)), ("energy", c_int32)]
 
 
 class MaskDesc(ctypes.Structure):
@@ -67,7 +69,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n_params", c_int64), ("nnz", c_int64), ("n_chains", c_int32), ("precision", c_int32),
                 ("kind", c_int32), ("rows_per_tile_a", c_int32), ("rows_per_tile_b", c_int32),
                 ("tiles_a", c_int32), ("tiles_b", c_int32), ("device_bytes", c_int64),
-                ("threads_a", c_int32), ("threads_b", c_int32)]
+                ("threads_a", c_int32), ("threads_b", c_int32), ("energy_precision", c_int32)]
 
 
 STAT_DTYPE = np.dtype([("H0", "f8"), ("H1", "f8"), ("log_u", "f8"), ("accepted", "i4"), ("divergent", "i4")])
@@ -104,6 +106,10 @@ def load():
                            POINTER(Tuning)],
         "hmc_autotune": [POINTER(NetDesc), POINTER(MaskDesc), POINTER(DataDesc), c_int32, POINTER(Tuning),
                          POINTER(c_double)],
+        "hmc_adapt": [P, c_int64, POINTER(c_double), c_int32, c_double, POINTER(c_double)],
+        "hmc_calibrate": [P, c_int32, c_int64, POINTER(c_double), c_int32, c_double, POINTER(c_double),
+                          POINTER(c_double)],
+        "hmc_trajectory_length": [POINTER(c_double), c_int64, c_int32, c_double, POINTER(c_int32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -166,6 +172,18 @@ def sensitivities(*, widths_a, theta0, sigma, x=None, kind="mlp", widths_b=None,
     return out
 
 
+def trajectory_length(var, eps, mode="median"):
+    """Leapfrog steps L = round(pi * v / (2 eps)) of App. C (hmc_trajectory_length),
+    v the median ("median") or largest ("max") of the posterior variances var."""
+    lib = load()
+    v = _f64(np.atleast_1d(var))
+    out = c_int32(0)
+    st = lib.hmc_trajectory_length(_dptr(v), v.size, {"max": 0, "median": 1}[mode], float(eps), ctypes.byref(out))
+    if st != HMC_OK:
+        raise HMCError(st, lib.hmc_last_error(None).decode())
+    return int(out.value)
+
+
 def select_mask(s2, tau):
     """Indices (increasing) of the sensitive subset for threshold tau
     (hmc_select_mask)."""
@@ -180,7 +198,7 @@ def select_mask(s2, tau):
 
 
 def _descs(*, kind, widths_a, widths_b, theta0, prior_sd, lik_sd, precision, offs, idx, theta_init=None,
-           inv_mass=None, x=None, y=None, u=None, yq=None, v=None):
+           inv_mass=None, x=None, y=None, u=None, yq=None, v=None, energy="default"):
     """The C descriptors of a network, its masks and its data, and the arrays
     they point into (keep them alive while the descriptors are used)."""
     wa = np.ascontiguousarray(widths_a, dtype=np.int32)
@@ -193,7 +211,7 @@ def _descs(*, kind, widths_a, widths_b, theta0, prior_sd, lik_sd, precision, off
     net = NetDesc(KIND[kind], len(wa), wa.ctypes.data_as(POINTER(c_int32)),
                   len(wb) if widths_b is not None else 0, wb.ctypes.data_as(POINTER(c_int32)),
                   _dptr(th0), th0.size, float(prior_sd), float(lik_sd), PRECISION[precision],
-                  _dptr(minv) if minv is not None else None)
+                  _dptr(minv) if minv is not None else None, ENERGY[energy])
     mask = MaskDesc(len(offs) - 1, offs.ctypes.data_as(POINTER(c_int64)),
                     idx.ctypes.data_as(POINTER(c_int64)), _dptr(tinit) if tinit is not None else None)
     keep = [wa, wb, offs, idx, th0, minv, tinit]
@@ -208,10 +226,10 @@ def _descs(*, kind, widths_a, widths_b, theta0, prior_sd, lik_sd, precision, off
     return net, mask, data, keep
 
 
-def _workload_kwargs(w, precision=None):
+def _workload_kwargs(w, precision=None, energy=None):
     kw = dict(kind=w.kind, widths_a=w.widths_a, widths_b=w.widths_b, theta0=w.theta0,
               prior_sd=w.prior_sd, lik_sd=w.lik_sd, precision=precision or w.precision,
-              offs=w.offs, idx=w.idx, theta_init=w.theta_init)
+              offs=w.offs, idx=w.idx, theta_init=w.theta_init, energy=energy or w.energy)
     if w.kind == "mlp":
         kw.update(x=w.x, y=w.y)
     else:
@@ -245,7 +263,7 @@ class Sampler:
 
     def __init__(self, *, kind, widths_a, widths_b=None, theta0, prior_sd, lik_sd, precision,
                  offs, idx, theta_init=None, inv_mass=None, x=None, y=None, u=None, yq=None, v=None,
-                 seed=0, stream=None, tuning=None):
+                 seed=0, stream=None, tuning=None, energy="default"):
         self._lib = load()
         self._ctx = c_void_p()
         self.kind = kind
@@ -255,7 +273,8 @@ class Sampler:
         self._np_state = np.float64 if precision == "fp64" else np.float32
         net, mask, data, keep = _descs(kind=kind, widths_a=widths_a, widths_b=widths_b, theta0=theta0,
                                        prior_sd=prior_sd, lik_sd=lik_sd, precision=precision, offs=offs, idx=idx,
-                                       theta_init=theta_init, inv_mass=inv_mass, x=x, y=y, u=u, yq=yq, v=v)
+                                       theta_init=theta_init, inv_mass=inv_mass, x=x, y=y, u=u, yq=yq, v=v,
+                                       energy=energy)
         self.offs = keep[2]
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream().cuda_stream
@@ -276,8 +295,8 @@ class Sampler:
         self.n_chains = int(info.n_chains)
 
     @classmethod
-    def from_workload(cls, w, *, seed=0, precision=None, stream=None, inv_mass=None, tuning=None):
-        kw = _workload_kwargs(w, precision)
+    def from_workload(cls, w, *, seed=0, precision=None, stream=None, inv_mass=None, tuning=None, energy=None):
+        kw = _workload_kwargs(w, precision, energy)
         kw.update(inv_mass=inv_mass, seed=seed, stream=stream, tuning=tuning)
         return cls(**kw)
 
@@ -343,6 +362,27 @@ class Sampler:
         st = np.frombuffer(bytes(stats), dtype=STAT_DTYPE).reshape(n, self.n_chains) if want_stats else None
         return out, st
 
+    def adapt(self, n, eps0, L, target=0.8):
+        """n iterations of step-size adaptation on the device (hmc_adapt): each
+        chain's step size by dual averaging toward the target acceptance rate;
+        returns the per-chain averaged step sizes (float64 numpy).  The
+        chains move."""
+        e = self._eps_array(eps0, self.n_chains)
+        out = np.empty(self.n_chains)
+        torch.cuda.synchronize()
+        self._check(self._lib.hmc_adapt(self._ctx, int(n), _dptr(e), int(L), float(target), _dptr(out)))
+        return out
+
+    def calibrate(self, rounds, batch, eps, L, target=0.8):
+        """Bisection of every chain's step size on the batch-mean acceptance
+        probability (hmc_calibrate); returns (step sizes, last batch means)."""
+        e = self._eps_array(eps, self.n_chains)
+        out, acc = np.empty(self.n_chains), np.empty(self.n_chains)
+        torch.cuda.synchronize()
+        self._check(self._lib.hmc_calibrate(self._ctx, int(rounds), int(batch), _dptr(e), int(L), float(target),
+                                            _dptr(out), _dptr(acc)))
+        return out, acc
+
     def get_state(self):
         th = self._state_tensor()
         U = np.empty(self.n_chains)
@@ -390,8 +430,8 @@ class Sampler:
         mean = np.empty(shape)
         var = np.empty(shape)
         torch.cuda.synchronize()
-        self._check(self._lib.hmc_predict(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]),
-                                          ctypes.byref(data), _dptr(mean), _dptr(var)))
+        self._check(self._lib.hmc_predict(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]), ctypes.byref(data),
+                       _dptr(mean), _dptr(var)))
         del keep
         return mean, var
 

@@ -98,19 +98,17 @@ struct hmc_ctx {
     int max_n = 0;
     int upd_sub = 1;          // threads per entry of k_update (update_sub)
     int Ra = 0, Rb = 0, tiles_a = 0, tiles_b = 0;
+    bool alias_a = false, alias_b = false;   // slabs 1 and 3 shared (a_1 recomputed in the adjoint pass)
     int grid_a = 0, grid_b = 0;
     size_t lds_a = 0, lds_b = 0;
     int nt_a = 256, nt_b = 256, nt_a32 = 256, nt_b32 = 256;   // threads per workgroup
-    // resident MLP kernel (weights in LDS, several tiles per workgroup)
-    bool resident = false;
     bool force_dense = false;     // sensitivity engines: dense dW (squared terms) on every layer
     hmc_tuning tune{0, 0, 0, 0};  // launch-shape overrides (0: automatic)
-    int kpt = 0, groups = 0, grid_res = 0;
-    size_t lds_res = 0;
     GradArgs ga{};
     StateArgs sa{};
     // BF16 and split-BF16 engines: FP32 energy pass over an FP32 shadow of the weights
-    bool energy32 = false;
+    bool energy32 = false;     // a separate energy pass (its plan and buffers: ga32 and the *32 fields)
+    int eprec = HMC_FP32;      // its precision: HMC_FP32, or HMC_FP64 on request
     GradArgs ga32{};
     int Ra32 = 0, Rb32 = 0, tiles_a32 = 0, tiles_b32 = 0, grid_a32 = 0, grid_b32 = 0;
     size_t lds_a32 = 0, lds_b32 = 0;
@@ -175,6 +173,7 @@ hmc_status validate(const hmc_net_desc* net, const hmc_mask_desc* mask, const hm
     if (!net || !mask || !data) { err = "net, mask and data must be non-NULL"; return HMC_EINVAL; }
     if (net->kind != HMC_MLP && net->kind != HMC_DEEPONET) { err = "unknown network kind"; return HMC_EINVAL; }
     if (net->precision < HMC_FP64 || net->precision > HMC_BF16X3) { err = "unknown precision"; return HMC_EINVAL; }
+    if (net->energy != HMC_ENERGY_DEFAULT && net->energy != HMC_ENERGY_FP64) { err = "unknown energy"; return HMC_EINVAL; }
     HMC_TRY(check_tower(net->widths_a, net->n_widths_a, "widths_a", err));
     std::vector<int> wa(net->widths_a, net->widths_a + net->n_widths_a), wb;
     long long P = tower_count(wa);
@@ -243,22 +242,41 @@ int pick_threads(size_t /*lds*/, int forced) {
     return 512;
 }
 
-size_t tower_lds(const std::vector<int>& w, int prec, int R) {
+// Slab sharing (recompute) applies to towers with at least four linear
+// layers, where slab 3 holds a hidden activation.
+bool can_alias(const std::vector<int>& w) { return w.size() >= 5; }
+
+// LDS row stride (elements) of slab l.
+int slab_ld(const std::vector<int>& w, int prec, size_t l) { return roundup(w[l], pad_of(prec)) + lpad_of(prec); }
+
+// Bytes of a tower's activation slabs at R rows; alias: slabs 1 and 3 share
+// one region of the larger stride.
+size_t tower_lds(const std::vector<int>& w, int prec, int R, bool alias = false) {
     size_t e = 0;
-    for (int x : w) e += (size_t)R * (roundup(x, pad_of(prec)) + lpad_of(prec));
+    for (size_t l = 0; l < w.size(); ++l) {
+        if (alias && l == 3) continue;
+        int ld = slab_ld(w, prec, l);
+        if (alias && l == 1) ld = std::max(ld, slab_ld(w, prec, 3));
+        e += (size_t)R * ld;
+    }
     return e * tsize_of(prec);
 }
 
-void fill_plan(TowerPlan& tp, const std::vector<int>& w, int prec, int R) {
+void fill_plan(TowerPlan& tp, const std::vector<int>& w, int prec, int R, bool alias = false) {
     std::memset(&tp, 0, sizeof(tp));
     tp.nl = (int)w.size() - 1;
+    tp.rc1 = alias ? 1 : 0;
     int off = 0;
     for (size_t l = 0; l < w.size(); ++l) {
         tp.w[l] = w[l];
         tp.wp[l] = roundup(w[l], pad_of(prec));
-        tp.ls[l] = tp.wp[l] + lpad_of(prec);
+        tp.ls[l] = slab_ld(w, prec, l);
+        if (alias && l == 3) {
+            tp.lo[l] = tp.lo[1];
+            continue;
+        }
         tp.lo[l] = off;
-        off += R * tp.ls[l];
+        off += R * (alias && l == 1 ? std::max(tp.ls[1], slab_ld(w, prec, 3)) : tp.ls[l]);
     }
 }
 
@@ -283,17 +301,17 @@ size_t bias_bytes(const std::vector<int>& w, int prec, size_t as) {
     return (n * as + 15) / 16 * 16;
 }
 
-size_t energy_lds(const TowerPlan& src, int R) {
+size_t energy_lds(const TowerPlan& src, int R, size_t es) {
     int mx = 0;
     for (int l = 0; l <= src.nl; ++l) mx = std::max(mx, src.wp[l] + 4);
-    return ((size_t)2 * R * mx * 4 + 15) / 16 * 16;
+    return ((size_t)2 * R * mx * es + 15) / 16 * 16;
 }
 
 // fixed: bytes beside the slabs (staged biases); per_row: bytes per tile row
-// (staged targets).
-int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
+// (staged targets); es: bytes per element of the energy pass.
+int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row, size_t es) {
     for (int R : {64, 32, 16})
-        if (energy_lds(src, R) + 64 + fixed + per_row * R <= g_lds_cap) return R;
+        if (energy_lds(src, R, es) + 64 + fixed + per_row * R <= g_lds_cap) return R;
     return 0;
 }
 
@@ -304,11 +322,21 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row) {
 // of 16).  A tuning value (16, 32 or 64; 0 when it does not fit) or else
 // HMC_ROWS_A / HMC_ROWS_B overrides it.
 // fixed: bytes beside the slabs (staged biases, alignment).
+// A tower that fits at no tile height with all its slabs shares slabs 1 and
+// 3 (alias, recomputing a_1 in the adjoint pass: one tile product of the
+// narrow input layer) when it has four or more layers.
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
-              const char* env, int forced) {
+              const char* env, int forced, bool& alias) {
+    alias = false;
     auto fits = [&](int r) {
-        return tower_lds(w, prec, r) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed <= g_lds_cap;
+        return tower_lds(w, prec, r, alias) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed <= g_lds_cap;
     };
+    auto any_fits = [&]() { return fits(16) || fits(32) || fits(64); };
+    const char* rc = std::getenv("HMC_RECOMPUTE");   // "1": share wherever possible (tests)
+    if (can_alias(w) && ((rc && !std::strcmp(rc, "1")) || !any_fits())) {
+        alias = true;
+        if (!any_fits()) alias = false;
+    }
     if (forced) return fits(forced) ? forced : 0;
     if (const char* s = std::getenv(env)) {
         const int r = std::atoi(s);
@@ -323,9 +351,7 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
 
 hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
     const int P = x->prec;
-    if (x->resident) {
-        HMC_HIP(x, hmc_launch_mlp_res(P, x->Ra, x->kpt, x->ga, x->grid_res, x->lds_res, s));
-    } else if (x->kind == HMC_MLP) {
+    if (x->kind == HMC_MLP) {
         HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, s));
     } else {
         HMC_HIP(x, hmc_launch_trunk_fwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, s));
@@ -355,10 +381,10 @@ int update_grid(const hmc_ctx* x) { return (x->max_n + 256 / x->upd_sub - 1) / (
 hmc_status launch_energy(hmc_ctx* x, hipStream_t s) {
     if (!x->energy32) return HMC_OK;
     if (x->kind == HMC_MLP) {
-        HMC_HIP(x, hmc_launch_mlp_energy(x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
+        HMC_HIP(x, hmc_launch_mlp_energy(x->eprec, x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
     } else {
-        HMC_HIP(x, hmc_launch_trunk_fwd(HMC_FP32, x->Rb32, x->nt_b32, x->ga32, x->grid_b32, x->lds_b32, s));
-        HMC_HIP(x, hmc_launch_branch_energy(x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
+        HMC_HIP(x, hmc_launch_trunk_fwd(x->eprec, x->Rb32, x->nt_b32, x->ga32, x->grid_b32, x->lds_b32, s));
+        HMC_HIP(x, hmc_launch_branch_energy(x->eprec, x->Ra32, x->nt_a32, x->ga32, x->grid_a32, x->lds_a32, s));
     }
     return HMC_OK;
 }
@@ -428,14 +454,15 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     if (x->kind == HMC_MLP) {
         rows_a = data->n_rows;
         x->Ra = pick_rows(x->A.w, prec, (size_t)x->A.w.back() * 8, bias_bytes(x->A.w, prec, as), rows_a, x->C,
-                          "HMC_ROWS_A", x->tune.rows_a);
+                          "HMC_ROWS_A", x->tune.rows_a, x->alias_a);
     } else {
         rows_a = data->n_u;
         rows_b = data->n_q;
         nq_pad = roundup((int)rows_b, pad);
         x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, bias_bytes(x->A.w, prec, as), rows_a,
-                          x->C, "HMC_ROWS_A", x->tune.rows_a);
-        x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B", x->tune.rows_b);
+                          x->C, "HMC_ROWS_A", x->tune.rows_a, x->alias_a);
+        x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B", x->tune.rows_b,
+                          x->alias_b);
         if (!x->Rb)
             return x->fail(HMC_EUNSUPPORTED, x->tune.rows_b ? "trunk tower does not fit in LDS at the requested rows per tile"
                                                             : "trunk tower does not fit in LDS");
@@ -451,11 +478,11 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     x->grid_b = roundup(x->C * x->tiles_b, 8);
 
     GradArgs& g = x->ga;
-    fill_plan(g.ta, x->A.w, prec, x->Ra);
+    fill_plan(g.ta, x->A.w, prec, x->Ra, x->alias_a);
     g.ta.seg0 = 0;
     for (int l = 0; l < la; ++l) g.ta.fo[l] = x->A.lstart[l];
     if (x->kind == HMC_DEEPONET) {
-        fill_plan(g.tb, x->B.w, prec, x->Rb);
+        fill_plan(g.tb, x->B.w, prec, x->Rb, x->alias_b);
         g.tb.seg0 = la;
         for (int l = 0; l < lb; ++l) g.tb.fo[l] = x->B.lstart[l];
     }
@@ -555,7 +582,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
 
     // LDS: activation slabs [+ output-adjoint slab] + reduction scratch +
     // per-chain tables (TileMeta) + staged biases [+ MLP targets].
-    x->lds_a = tower_lds(x->A.w, prec, x->Ra);
+    x->lds_a = tower_lds(x->A.w, prec, x->Ra, x->alias_a);
     if (x->kind == HMC_DEEPONET) {
         g.dg_off = (int)(x->lds_a / ts);
         g.dg_ld = nq_pad + lpad_of(prec);
@@ -575,7 +602,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
     x->nt_a = pick_threads(x->lds_a, x->tune.threads);
     if (x->kind == HMC_DEEPONET) {
-        x->lds_b = (tower_lds(x->B.w, prec, x->Rb) + 15) / 16 * 16 + 64;
+        x->lds_b = (tower_lds(x->B.w, prec, x->Rb, x->alias_b) + 15) / 16 * 16 + 64;
         g.meta_lds_b = (int)x->lds_b;
         x->lds_b += HMC_META_BYTES;
         g.bias_lds_b = (int)x->lds_b;
@@ -644,45 +671,6 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             }
         }
     }
-    // Resident MLP kernel (HMC_RESIDENT=1): the padded weights (rows padded by
-    // 16 bytes) and the activation slabs fit in LDS, and every chain has at
-    // most 8 selected entries per thread.  Tiles per workgroup are chosen so
-    // that the grid is about one workgroup per compute unit.  Measured on the
-    // FP32 MLP workload it is slower than one tile per workgroup (the tiles of
-    // a workgroup run one after another at one workgroup per compute unit), so
-    // it is opt-in.
-    if (x->kind == HMC_MLP && !x->force_dense && prec != HMC_BF16X3 && x->max_n <= 8 * HMC_NT &&
-        std::getenv("HMC_RESIDENT") &&
-        !std::strcmp(std::getenv("HMC_RESIDENT"), "1")) {
-        const int E = (int)(16 / ts);
-        long long wl = 0;
-        TowerPlan& tp = g.ta;
-        for (int l = 0; l < tp.nl; ++l) {
-            tp.lwo[l] = (int)wl;
-            wl += (long long)tp.wp[l + 1] * (tp.wp[l] + E);
-            tp.lwto[l] = (int)wl;
-            wl += (long long)tp.wp[l] * (tp.wp[l + 1] + E);
-        }
-        const size_t acts = (tower_lds(x->A.w, prec, x->Ra) + 15) / 16 * 16;
-        const size_t need = acts + (size_t)wl * ts + 64;
-        if (need <= g_lds_cap) {
-            int cus = 0;
-            HMC_HIP(x, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device));
-            if (cus <= 0) cus = 256;
-            const long long total = (long long)x->C * x->tiles_a;
-            const int tpw = (int)std::max(1ll, (total + cus - 1) / cus);
-            x->resident = true;
-            x->kpt = x->max_n <= 4 * HMC_NT ? 4 : 8;
-            x->groups = (x->tiles_a + tpw - 1) / tpw;
-            x->grid_res = roundup(x->C * x->groups, 8);
-            g.tpw = tpw;
-            g.groups = x->groups;
-            g.w_lds_off = (int)(acts / ts);
-            g.red_off = (int)(acts + (size_t)wl * ts);
-            x->lds_res = need;
-        }
-    }
-
     // Per layer: where its bias entries start, and whether its weight partials
     // come from a dense tile product (MFMA over the tile rows, selected
     // entries picked through the layer's selection bitmap) or from per-entry
@@ -808,48 +796,78 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.ecode = code_d;
     g.seg = seg_d;
     g.nseg = nseg;
-    g.tmax = x->resident ? x->groups : std::max(x->tiles_a, x->tiles_b);
+    g.tmax = std::max(x->tiles_a, x->tiles_b);
     g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
-    g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * (x->resident ? x->groups : x->tiles_a));
+    g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * x->tiles_a);
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
 
-    // BF16 and split-BF16 engines: FP32 shadow for the energy pass (same
-    // offsets as wbuf).
-    // Built after every field of the BF16 arguments is final, since the
+    // Separate energy pass: BF16 and split-BF16 engines always (an FP32 or,
+    // on request, FP64 forward pass), FP32 engines when FP64 energies are
+    // requested.  Its weights are a shadow of wbuf in the energy precision
+    // with the same offsets (one scatter writes both); with FP64 energies the
+    // biases get an FP64 shadow too.
+    // Built after every field of the product arguments is final, since the
     // energy arguments start as a copy of them.
     void* w32 = nullptr;
-    if (prec == HMC_BF16 || prec == HMC_BF16X3) {
+    void* b64 = nullptr;
+    if (prec == HMC_BF16 || prec == HMC_BF16X3 || (prec == HMC_FP32 && net->energy == HMC_ENERGY_FP64)) {
         x->energy32 = true;
+        x->eprec = net->energy == HMC_ENERGY_FP64 ? HMC_FP64 : HMC_FP32;
+        const char* ename = x->eprec == HMC_FP64 ? "FP64" : "FP32";
+        const size_t es = tsize_of(x->eprec);
         GradArgs& e = x->ga32;
         e = g;
-        x->Ra32 = pick_rows_energy(g.ta, bias_bytes(x->A.w, prec, 4), x->kind == HMC_MLP ? (size_t)x->A.w.back() * 8 : 0);
-        if (!x->Ra32) return x->fail(HMC_EUNSUPPORTED, "tower does not fit in LDS for the FP32 energy pass");
+        x->Ra32 = pick_rows_energy(g.ta, bias_bytes(x->A.w, prec, es), x->kind == HMC_MLP ? (size_t)x->A.w.back() * 8 : 0,
+                                   es);
+        if (!x->Ra32) return x->fail(HMC_EUNSUPPORTED, std::string("tower does not fit in LDS for the ") + ename + " energy pass");
         fill_plan_energy(e.ta, g.ta, x->Ra32);
         x->tiles_a32 = (int)((rows_a + x->Ra32 - 1) / x->Ra32);
         x->grid_a32 = roundup(x->C * x->tiles_a32, 8);
-        x->lds_a32 = energy_lds(g.ta, x->Ra32);
+        x->lds_a32 = energy_lds(g.ta, x->Ra32, es);
         e.red_off = (int)x->lds_a32;
         x->lds_a32 += 64;
         e.bias_lds_a = (int)x->lds_a32;
-        x->lds_a32 += bias_bytes(x->A.w, prec, 4);
+        x->lds_a32 += bias_bytes(x->A.w, prec, es);
         e.y_lds = (int)x->lds_a32;
         if (x->kind == HMC_MLP) x->lds_a32 += (size_t)x->Ra32 * x->A.w.back() * 8;
         x->nt_a32 = pick_threads(x->lds_a32, x->tune.threads);
         {
-            std::vector<unsigned char> w32h((size_t)g.wstride * 4, 0);
-            fill_tower(w32h, HMC_FP32, g.ta, x->A);
-            if (x->kind == HMC_DEEPONET) fill_tower(w32h, HMC_FP32, g.tb, x->B);
-            w32 = x->dalloc((size_t)x->C * g.wstride * 4);
-            if (!w32) return x->fail(HMC_ENOMEM, "device allocation of the FP32 weight shadow failed");
+            std::vector<unsigned char> w32h((size_t)g.wstride * es, 0);
+            fill_tower(w32h, x->eprec, g.ta, x->A);
+            if (x->kind == HMC_DEEPONET) fill_tower(w32h, x->eprec, g.tb, x->B);
+            w32 = x->dalloc((size_t)x->C * g.wstride * es);
+            if (!w32) return x->fail(HMC_ENOMEM, "device allocation of the energy weight shadow failed");
             for (int c = 0; c < x->C; ++c)
-                HMC_HIP(x, hipMemcpy((char*)w32 + (size_t)c * g.wstride * 4, w32h.data(), w32h.size(),
+                HMC_HIP(x, hipMemcpy((char*)w32 + (size_t)c * g.wstride * es, w32h.data(), w32h.size(),
                                      hipMemcpyHostToDevice));
             e.wbuf = w32;
         }
-        auto upload32 = [&](const double* src, long long rows, int w, int wp, int R, int tiles) -> void* {
-            std::vector<unsigned char> h((size_t)tiles * R * wp * 4, 0);
+        if (x->eprec == HMC_FP64) {
+            // FP64 biases (and b0) in the product buffer's layout
+            std::vector<unsigned char> b64h((size_t)g.bstride * 8, 0);
+            auto fill_b = [&](const TowerPlan& tp, const TowerHost& th) {
+                for (int l = 0; l < tp.nl; ++l) {
+                    const int in = tp.w[l], out = tp.w[l + 1];
+                    for (int i = 0; i < out; ++i)
+                        put_a(b64h, HMC_FP64, (size_t)(tp.bo[l] + i), net->theta0[th.lstart[l] + (long long)out * in + i]);
+                }
+            };
+            fill_b(g.ta, x->A);
+            if (x->kind == HMC_DEEPONET) {
+                fill_b(g.tb, x->B);
+                put_a(b64h, HMC_FP64, (size_t)g.b0_off, net->theta0[x->P - 1]);
+            }
+            b64 = x->dalloc((size_t)x->C * g.bstride * 8);
+            if (!b64) return x->fail(HMC_ENOMEM, "device allocation of the FP64 bias shadow failed");
+            for (int c = 0; c < x->C; ++c)
+                HMC_HIP(x, hipMemcpy((char*)b64 + (size_t)c * g.bstride * 8, b64h.data(), b64h.size(),
+                                     hipMemcpyHostToDevice));
+            e.bbuf = b64;
+        }
+        auto upload_e = [&](const double* src, long long rows, int w, int wp, int R, int tiles) -> void* {
+            std::vector<unsigned char> h((size_t)tiles * R * wp * es, 0);
             for (long long r = 0; r < rows; ++r)
-                for (int j = 0; j < w; ++j) put_t(h, HMC_FP32, (size_t)(r * wp + j), src[r * w + j]);
+                for (int j = 0; j < w; ++j) put_t(h, x->eprec, (size_t)(r * wp + j), src[r * w + j]);
             void* d = x->dalloc(h.size());
             if (d && hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
             return d;
@@ -857,30 +875,30 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         e.tiles_a = x->tiles_a32;
         e.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * x->tiles_a32);
         if (x->kind == HMC_MLP) {
-            e.xa = upload32(data->x, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
+            e.xa = upload_e(data->x, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
         } else {
-            e.xa = upload32(data->u, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
-            x->Rb32 = pick_rows_energy(g.tb, bias_bytes(x->B.w, prec, 4), 0);
-            if (!x->Rb32) return x->fail(HMC_EUNSUPPORTED, "trunk does not fit in LDS for the FP32 energy pass");
+            e.xa = upload_e(data->u, rows_a, x->A.w[0], g.ta.wp[0], x->Ra32, x->tiles_a32);
+            x->Rb32 = pick_rows_energy(g.tb, bias_bytes(x->B.w, prec, es), 0, es);
+            if (!x->Rb32) return x->fail(HMC_EUNSUPPORTED, std::string("trunk does not fit in LDS for the ") + ename + " energy pass");
             fill_plan_energy(e.tb, g.tb, x->Rb32);
             x->tiles_b32 = (int)((rows_b + x->Rb32 - 1) / x->Rb32);
             x->grid_b32 = roundup(x->C * x->tiles_b32, 8);
-            x->lds_b32 = energy_lds(g.tb, x->Rb32) + 64;
+            x->lds_b32 = energy_lds(g.tb, x->Rb32, es) + 64;
             e.bias_lds_b = (int)x->lds_b32;
-            x->lds_b32 += bias_bytes(x->B.w, prec, 4);
+            x->lds_b32 += bias_bytes(x->B.w, prec, es);
             x->nt_b32 = pick_threads(x->lds_b32, x->tune.threads);
             e.tiles_b = x->tiles_b32;
-            e.xb = upload32(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);
+            e.xb = upload_e(data->yq, rows_b, x->B.w[0], g.tb.wp[0], x->Rb32, x->tiles_b32);
             const int pp = g.ta.wp[la];
             e.nq_rows = std::max(nq_pad, x->tiles_b32 * x->Rb32);
             e.tm_stride = (long long)e.nq_rows * pp;
-            e.tm = x->dalloc((size_t)x->C * e.tm_stride * 4);
-            e.tt = x->dalloc((size_t)x->C * e.tm_stride * 4);
+            e.tm = x->dalloc((size_t)x->C * e.tm_stride * es);
+            e.tt = x->dalloc((size_t)x->C * e.tm_stride * es);
             if (!e.xb || !e.tm || !e.tt) return x->fail(HMC_ENOMEM, "device allocation of the energy pass failed");
         }
         if (!e.xa || !e.ulik) return x->fail(HMC_ENOMEM, "device allocation of the energy pass failed");
-        HMC_HIP(x, hmc_set_lds_limit(HMC_FP32, x->Ra32, g_lds_cap));
-        if (x->Rb32) HMC_HIP(x, hmc_set_lds_limit(HMC_FP32, x->Rb32, g_lds_cap));
+        HMC_HIP(x, hmc_set_lds_limit(x->eprec, x->Ra32, g_lds_cap));
+        if (x->Rb32) HMC_HIP(x, hmc_set_lds_limit(x->eprec, x->Rb32, g_lds_cap));
     }
 
     // Chain state.
@@ -892,14 +910,16 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.nseg = nseg;
     s.seg_trunk_lo = la;
     s.seg_trunk_hi = la + lb;
-    s.tiles_a = x->resident ? x->groups : x->tiles_a;   // partials per chain and tower
+    s.tiles_a = x->tiles_a;   // partials per chain and tower
     s.tiles_b = x->tiles_b;
     s.tmax = g.tmax;
     x->upd_sub = update_sub(x);
     s.part = g.part;
     s.ulik = x->energy32 ? x->ga32.ulik : g.ulik;
-    s.ulik_tiles = x->energy32 ? x->tiles_a32 : (x->resident ? x->groups : x->tiles_a);
+    s.ulik_tiles = x->energy32 ? x->tiles_a32 : x->tiles_a;
     s.wbuf32 = w32;
+    s.w32_f64 = x->eprec == HMC_FP64 ? 1 : 0;
+    s.bbuf64 = b64;
     s.dst = dst_d;
     s.wbuf = wd;
     s.wstride = g.wstride;
@@ -915,7 +935,10 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.grad_save = x->dalloc(sb);
     x->pin = x->dalloc(sb);
     x->ptmp = x->dalloc(sb);
-    s.eps = (const double*)x->dalloc(sizeof(double) * x->C);
+    s.eps = (double*)x->dalloc(sizeof(double) * x->C);
+    s.da = (double*)x->dalloc(sizeof(double) * 4 * x->C);
+    s.adapt_on = (const int*)x->dalloc(sizeof(int));
+    s.da_cfg = (const double*)x->dalloc(sizeof(double) * 4);
     s.U = (double*)x->dalloc(sizeof(double) * x->C);
     s.U_save = (double*)x->dalloc(sizeof(double) * x->C);
     s.H0 = (double*)x->dalloc(sizeof(double) * x->C);
@@ -924,7 +947,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.stats = x->dalloc(sizeof(hmc_traj_stat) * x->C);
     s.n_acc = (long long*)x->dalloc(sizeof(long long) * x->C);
     s.n_div = (long long*)x->dalloc(sizeof(long long) * x->C);
-    if (!s.theta || !s.mom || !s.grad || !s.theta_save || !s.grad_save || !x->pin || !x->ptmp || !s.eps || !s.U ||
+    if (!s.theta || !s.mom || !s.grad || !s.theta_save || !s.grad_save || !x->pin || !x->ptmp || !s.eps || !s.da ||
+        !s.adapt_on || !s.da_cfg || !s.U ||
         !s.U_save || !s.H0 || !s.H1 || !s.iter || !s.stats || !s.n_acc || !s.n_div)
         return x->fail(HMC_ENOMEM, "device allocation of the chain state failed");
     std::vector<unsigned char> th(sb);
@@ -1198,6 +1222,7 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
     hmc_net_desc n2 = *net;
     if (n2.precision == HMC_BF16 || n2.precision == HMC_BF16X3) n2.precision = HMC_FP32;
     n2.inv_mass_diag = nullptr;
+    n2.energy = HMC_ENERGY_DEFAULT;
     hmc_mask_desc m{1, offs.data(), idx.data(), nullptr};
     // targets are not used; the engine keeps a zero array in their place
     hmc_data_desc d2 = *data;
@@ -1303,9 +1328,32 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
     return done(HMC_OK);
 }
 
-hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
-                       const hmc_data_desc* inputs, double* mean, double* var) {
-    if (!x) return HMC_EINVAL;
+namespace {
+
+// Device buffers of one prediction call: from hipMalloc (freed on return),
+// or carved in order from a fixed region (no allocation).
+struct PredictBuffers {
+    char* region = nullptr;        // fixed region, or null: allocate
+    size_t cap = 0, used = 0;
+    std::vector<void*> owned;
+    void* get(size_t bytes) {
+        bytes = (std::max<size_t>(bytes, 16) + 255) / 256 * 256;
+        if (region) {
+            if (used + bytes > cap) return nullptr;
+            void* p = region + used;
+            used += bytes;
+            return p;
+        }
+        void* d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess) return nullptr;
+        owned.push_back(d);
+        return d;
+    }
+    ~PredictBuffers() { for (void* d : owned) (void)hipFree(d); }
+};
+
+hmc_status predict_check(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
+                         const hmc_data_desc* inputs, const double* mean) {
     const bool deep = x->kind == HMC_DEEPONET;
     if (chain < 0 || chain >= x->C) return x->fail(HMC_EINVAL, "chain out of range");
     if (!samples || n_samples < 1) return x->fail(HMC_EINVAL, "samples must not be NULL and n_samples >= 1");
@@ -1316,14 +1364,24 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
                  inputs->n_q > (1ll << 24)))
         return x->fail(HMC_EINVAL, "DeepONet inputs need u, yq and 1 <= n_u, n_q <= 2^24");
     if (!mean) return x->fail(HMC_EINVAL, "mean must not be NULL");
-    // BF16 and split-BF16 engines predict through the FP32 energy-pass plan
+    return HMC_OK;
+}
+
+// The posterior predictive moments of hmc_predict with its device buffers
+// from buf (cap_check: fail with HMC_EUNSUPPORTED before any device work
+// when they do not fit a fixed region).
+hmc_status predict_impl(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
+                        const hmc_data_desc* inputs, double* mean, double* var, PredictBuffers& buf) {
+    HMC_TRY(predict_check(x, chain, samples, n_samples, inputs, mean));
+    const bool deep = x->kind == HMC_DEEPONET;
+    // engines with a separate energy pass predict through its plan (FP32 or FP64)
     const bool f32 = x->energy32;
-    const int P = f32 ? (int)HMC_FP32 : x->prec;
+    const int P = f32 ? x->eprec : x->prec;
     GradArgs g = f32 ? x->ga32 : x->ga;
     const int Ra = f32 ? x->Ra32 : x->Ra, Rb = f32 ? x->Rb32 : x->Rb;
     const int nta = f32 ? x->nt_a32 : x->nt_a, ntb = f32 ? x->nt_b32 : x->nt_b;
     const size_t ldsa = f32 ? x->lds_a32 : x->lds_a, ldsb = f32 ? x->lds_b32 : x->lds_b;
-    const size_t ts = f32 ? 4 : tsize_of(x->prec), ss = ssize_of(x->prec), as = asize_of(x->prec);
+    const size_t ts = tsize_of(P), ss = ssize_of(x->prec), as = f32 && x->eprec == HMC_FP64 ? 8 : asize_of(x->prec);
     const long long o = x->offs[chain], nc = x->offs[chain + 1] - o;
     // new inputs in the tile layout of the training rows (padded rows and widths)
     auto tiled = [&](const double* src, long long rows, int w, int wp, int R, std::vector<unsigned char>& h) {
@@ -1337,27 +1395,29 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
     const int la = (int)x->A.w.size() - 1;
     const int wpo = g.ta.wp[la];
     const size_t no = deep ? (size_t)ra * rb : (size_t)ra * x->A.w.back();
+    if (buf.region) {
+        // the whole need, each piece rounded as get() rounds it, against the region
+        auto r256 = [](size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; };
+        const size_t tra = (size_t)((ra + Ra - 1) / Ra) * Ra * g.ta.wp[0] * ts;
+        const size_t trb = deep ? (size_t)((rb + Rb - 1) / Rb) * Rb * g.tb.wp[0] * ts : 0;
+        size_t need = r256(tra) + r256((size_t)nc * ss) + r256(sizeof(double) * 3 * no);
+        if (deep) need += r256(trb) + r256((size_t)ra * wpo * ts) + r256((size_t)rb * wpo * ts);
+        if (need > buf.cap - buf.used)
+            return x->fail(HMC_EUNSUPPORTED, "the prediction needs " + std::to_string(need) +
+                                                 " bytes of device scratch, more than the fixed " +
+                                                 std::to_string(buf.cap) + " bytes");
+    }
     std::vector<unsigned char> ha, hb;
     const int tiles_a = tiled(deep ? inputs->u : inputs->x, ra, x->A.w[0], g.ta.wp[0], Ra, ha);
     const int tiles_b = deep ? tiled(inputs->yq, rb, x->B.w[0], g.tb.wp[0], Rb, hb) : 0;
-    std::vector<void*> tmp;
-    auto dev = [&](size_t bytes) -> void* {
-        void* d = nullptr;
-        if (hipMalloc(&d, bytes ? bytes : 16) != hipSuccess) return nullptr;
-        tmp.push_back(d);
-        return d;
-    };
-    auto cleanup = [&]() { for (void* d : tmp) (void)hipFree(d); };
-    void* xa = dev(ha.size());
-    void* xb = deep ? dev(hb.size()) : nullptr;
-    void* stage = dev((size_t)nc * ss);
-    double* mom = (double*)dev(sizeof(double) * 3 * no);   // mean, m2, var
-    void* Bn = deep ? dev((size_t)ra * wpo * ts) : nullptr;
-    void* Tn = deep ? dev((size_t)rb * wpo * ts) : nullptr;
-    if (!xa || !stage || !mom || (deep && (!xb || !Bn || !Tn))) {
-        cleanup();
+    void* xa = buf.get(ha.size());
+    void* xb = deep ? buf.get(hb.size()) : nullptr;
+    void* stage = buf.get((size_t)nc * ss);
+    double* mom = (double*)buf.get(sizeof(double) * 3 * no);   // mean, m2, var
+    void* Bn = deep ? buf.get((size_t)ra * wpo * ts) : nullptr;
+    void* Tn = deep ? buf.get((size_t)rb * wpo * ts) : nullptr;
+    if (!xa || !stage || !mom || (deep && (!xb || !Bn || !Tn)))
         return x->fail(HMC_ENOMEM, "device allocation for the predictions failed");
-    }
     // one chain's weights as a one-chain argument set over the new inputs
     g.wbuf = (const char*)g.wbuf + (size_t)chain * g.wstride * ts;
     g.bbuf = (const char*)g.bbuf + (size_t)chain * g.bstride * as;
@@ -1371,7 +1431,7 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
     const void* b0 = (const char*)g.bbuf + (size_t)g.b0_off * as;
     hipError_t e = hipMemcpyAsync(xa, ha.data(), ha.size(), hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess && deep) e = hipMemcpyAsync(xb, hb.data(), hb.size(), hipMemcpyHostToDevice, x->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(mom, 0, sizeof(double) * 3 * no, x->stream);
+    if (e == hipSuccess) e = hmc_launch_zero(mom, (long long)(3 * no), x->stream);
     for (int64_t k = 0; k < n_samples && e == hipSuccess; ++k) {
         const double inv_k = 1.0 / (double)(k + 1), inv_n = 1.0 / (double)n_samples;
         double* vout = k == n_samples - 1 ? mom + 2 * no : nullptr;
@@ -1395,9 +1455,17 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
     if (e == hipSuccess) e = hipMemcpyAsync(mean, mom, sizeof(double) * no, hipMemcpyDeviceToHost, x->stream);
     if (e == hipSuccess && var) e = hipMemcpyAsync(var, mom + 2 * no, sizeof(double) * no, hipMemcpyDeviceToHost, x->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
-    cleanup();
     if (e != hipSuccess) return x->fail(HMC_EDEVICE, std::string("HIP: ") + hipGetErrorString(e));
     return HMC_OK;
+}
+
+}  // namespace
+
+hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
+                       const hmc_data_desc* inputs, double* mean, double* var) {
+    if (!x) return HMC_EINVAL;
+    PredictBuffers buf;
+    return predict_impl(x, chain, samples, n_samples, inputs, mean, var, buf);
 }
 
 hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel) {
@@ -1480,6 +1548,148 @@ hmc_status hmc_sample(hmc_ctx* x, int64_t n, const double* eps, int32_t L, void*
         (void)hipHostFree(pinned);
     }
     return st;
+}
+
+namespace {
+
+// Starting step size of the adaptation for every chain (the heuristic that
+// Hoffman and Gelman's HMC with dual averaging starts from): from eps[c],
+// one leapfrog step with the chain's next momentum (the Philox stream of
+// its current iteration) gives the ratio exp(H0 - H1) (0 if not finite);
+// the step size doubles while the ratio stays above 1/2, or halves while it
+// stays below, and stops at the first step size where it crosses.  Each
+// probe is a one-step trajectory of the still-searching chains, with no
+// Metropolis step and the state restored.  At most 60 probes per chain.
+hmc_status reasonable_eps(hmc_ctx* x, std::vector<double>& eps) {
+    const int C = x->C;
+    std::vector<int> dir(C, 0), act(C, 1);
+    std::vector<double> H0(C), H1(C);
+    for (int probe = 0; probe <= 60; ++probe) {
+        HMC_TRY(set_eps_active(x, eps, act));
+        HMC_TRY(launch_leapfrog(x, x->sa, 1, x->stream));
+        HMC_HIP(x, hmc_launch_traj_end(x->prec, x->sa, END_TRAJ, x->stream));
+        HMC_HIP(x, hipMemcpyAsync(H0.data(), x->sa.H0, sizeof(double) * C, hipMemcpyDeviceToHost, x->stream));
+        HMC_HIP(x, hipMemcpyAsync(H1.data(), x->sa.H1, sizeof(double) * C, hipMemcpyDeviceToHost, x->stream));
+        HMC_HIP(x, hmc_launch_restore(x->prec, x->sa, x->stream));
+        HMC_HIP(x, hipStreamSynchronize(x->stream));
+        int left = 0;
+        for (int c = 0; c < C; ++c) {
+            if (!act[c]) continue;
+            const double d = std::isfinite(H1[c]) ? H0[c] - H1[c] : -INFINITY;   // log of the ratio
+            const bool above = d > -std::log(2.0);
+            if (probe == 0) dir[c] = above ? 1 : -1;
+            if ((dir[c] > 0) == above && probe < 60) {
+                eps[c] = dir[c] > 0 ? 2.0 * eps[c] : 0.5 * eps[c];
+                ++left;
+            } else {
+                act[c] = 0;
+            }
+        }
+        if (!left) break;
+    }
+    return HMC_OK;
+}
+
+}  // namespace
+
+hmc_status hmc_adapt(hmc_ctx* x, int64_t n, const double* eps0, int32_t L, double target, double* eps_out) {
+    if (!x) return HMC_EINVAL;
+    if (n < 1) return x->fail(HMC_EINVAL, "n must be positive");
+    if (!(target > 0.0 && target < 1.0)) return x->fail(HMC_EINVAL, "target must lie in (0, 1)");
+    if (!eps_out) return x->fail(HMC_EINVAL, "eps_out is NULL");
+    HMC_TRY(check_eps(x, eps0, x->C, L));
+    std::vector<double> e1(eps0, eps0 + x->C);
+    HMC_TRY(reasonable_eps(x, e1));
+    // gamma, t0 and kappa of Hoffman and Gelman (2014); mu = log(10 eps_1)
+    const double cfg[4] = {target, 0.05, 10.0, 0.75};
+    std::vector<double> da((size_t)4 * x->C, 0.0);
+    for (int c = 0; c < x->C; ++c) da[(size_t)4 * c + 3] = std::log(10.0 * e1[c]);
+    const int on = 1, off = 0;
+    HMC_HIP(x, hipMemcpyAsync((void*)x->sa.da_cfg, cfg, sizeof(cfg), hipMemcpyHostToDevice, x->stream));
+    HMC_HIP(x, hipMemcpyAsync(x->sa.da, da.data(), sizeof(double) * da.size(), hipMemcpyHostToDevice, x->stream));
+    HMC_TRY(set_eps_active(x, e1, std::vector<int>(x->C, 1)));
+    HMC_TRY(trajectory_graph(x, L));
+    HMC_HIP(x, hipMemcpyAsync((void*)x->sa.adapt_on, &on, sizeof(int), hipMemcpyHostToDevice, x->stream));
+    hmc_status st = HMC_OK;
+    for (int64_t i = 0; i < n && st == HMC_OK; ++i) st = x->hip(hipGraphLaunch(x->gexec, x->stream), "hipGraphLaunch");
+    // the flag goes off before any other work, also after a failed launch
+    const hmc_status s2 = x->hip(hipMemcpyAsync((void*)x->sa.adapt_on, &off, sizeof(int), hipMemcpyHostToDevice,
+                                                x->stream), "adapt flag");
+    HMC_TRY(st);
+    HMC_TRY(s2);
+    HMC_HIP(x, hipMemcpyAsync(da.data(), x->sa.da, sizeof(double) * da.size(), hipMemcpyDeviceToHost, x->stream));
+    HMC_HIP(x, hipStreamSynchronize(x->stream));
+    for (int c = 0; c < x->C; ++c) eps_out[c] = std::exp(da[(size_t)4 * c + 2]);
+    return HMC_OK;
+}
+
+hmc_status hmc_calibrate(hmc_ctx* x, int32_t rounds, int64_t batch, const double* eps_in, int32_t L, double target,
+                         double* eps_out, double* acc_out) {
+    if (!x) return HMC_EINVAL;
+    if (rounds < 1 || rounds > 64) return x->fail(HMC_EINVAL, "rounds must be in 1..64");
+    if (batch < 1) return x->fail(HMC_EINVAL, "batch must be positive");
+    if (!(target > 0.0 && target < 1.0)) return x->fail(HMC_EINVAL, "target must lie in (0, 1)");
+    if (!eps_out) return x->fail(HMC_EINVAL, "eps_out is NULL");
+    HMC_TRY(check_eps(x, eps_in, x->C, L));
+    const int C = x->C;
+    std::vector<double> lo(C, -INFINITY), hi(C, INFINITY), lx(C), acc(C, 0.0), eps(C);
+    for (int c = 0; c < C; ++c) lx[c] = std::log(eps_in[c]);
+    const double step = std::log(1.25);
+    HMC_TRY(trajectory_graph(x, L));
+    std::vector<double> da((size_t)4 * C, 0.0);
+    const int on = 2, off = 0;
+    for (int r = 0; r < rounds; ++r) {
+        for (int c = 0; c < C; ++c) eps[c] = std::exp(lx[c]);
+        std::fill(da.begin(), da.end(), 0.0);
+        HMC_HIP(x, hipMemcpyAsync(x->sa.da, da.data(), sizeof(double) * da.size(), hipMemcpyHostToDevice, x->stream));
+        HMC_TRY(set_eps_active(x, eps, std::vector<int>(C, 1)));
+        HMC_HIP(x, hipMemcpyAsync((void*)x->sa.adapt_on, &on, sizeof(int), hipMemcpyHostToDevice, x->stream));
+        hmc_status st = HMC_OK;
+        for (int64_t i = 0; i < batch && st == HMC_OK; ++i)
+            st = x->hip(hipGraphLaunch(x->gexec, x->stream), "hipGraphLaunch");
+        const hmc_status s2 = x->hip(hipMemcpyAsync((void*)x->sa.adapt_on, &off, sizeof(int), hipMemcpyHostToDevice,
+                                                    x->stream), "adapt flag");
+        HMC_TRY(st);
+        HMC_TRY(s2);
+        HMC_HIP(x, hipMemcpyAsync(da.data(), x->sa.da, sizeof(double) * da.size(), hipMemcpyDeviceToHost, x->stream));
+        HMC_HIP(x, hipStreamSynchronize(x->stream));
+        // bisection in log eps on the batch mean of the acceptance probability:
+        // too high -> the step size is a lower bound, too low -> an upper bound;
+        // before both bounds exist the step size moves by a factor 1.25
+        for (int c = 0; c < C; ++c) {
+            acc[c] = da[(size_t)4 * c] > 0 ? da[(size_t)4 * c + 1] / da[(size_t)4 * c] : 0.0;
+            if (acc[c] > target) lo[c] = lx[c];
+            else hi[c] = lx[c];
+            if (std::isfinite(lo[c]) && std::isfinite(hi[c])) lx[c] = 0.5 * (lo[c] + hi[c]);
+            else lx[c] += std::isfinite(lo[c]) ? step : -step;
+        }
+    }
+    for (int c = 0; c < C; ++c) {
+        eps_out[c] = std::exp(lx[c]);
+        if (acc_out) acc_out[c] = acc[c];
+    }
+    return HMC_OK;
+}
+
+hmc_status hmc_trajectory_length(const double* var, int64_t n, int32_t mode, double eps, int32_t* L) {
+    g_init_error.clear();
+    if (!var || !L || n < 1) { g_init_error = "var and L must not be NULL and n >= 1"; return HMC_EINVAL; }
+    if (mode != 0 && mode != 1) { g_init_error = "mode must be 0 (largest) or 1 (median)"; return HMC_EINVAL; }
+    if (!(eps > 0.0) || !std::isfinite(eps)) { g_init_error = "eps must be positive and finite"; return HMC_EINVAL; }
+    std::vector<double> v(var, var + n);
+    for (double a : v)
+        if (!(a >= 0.0) || !std::isfinite(a)) { g_init_error = "variances must be finite and >= 0"; return HMC_EINVAL; }
+    double pv;
+    if (mode == 0) {
+        pv = *std::max_element(v.begin(), v.end());
+    } else {
+        std::sort(v.begin(), v.end());
+        pv = n % 2 ? v[(size_t)n / 2] : 0.5 * (v[(size_t)n / 2 - 1] + v[(size_t)n / 2]);
+    }
+    const double steps = std::nearbyint(3.14159265358979323846 * pv / (2.0 * eps));
+    if (!(steps <= 1000000.0)) { g_init_error = "the rule gives more than 10^6 steps"; return HMC_EINVAL; }
+    *L = (int32_t)std::max(1.0, steps);
+    return HMC_OK;
 }
 
 hmc_status hmc_grad(hmc_ctx* x, double* U, void* g) {
@@ -1573,8 +1783,9 @@ hmc_status hmc_get_info(const hmc_ctx* x, hmc_info_t* info) {
     info->tiles_a = x->tiles_a;
     info->tiles_b = x->tiles_b;
     info->device_bytes = x->dev_bytes;
-    info->threads_a = x->resident ? HMC_NT : x->nt_a;
+    info->threads_a = x->nt_a;
     info->threads_b = x->kind == HMC_DEEPONET ? x->nt_b : 0;
+    info->energy_precision = x->energy32 ? x->eprec : x->prec;
     return HMC_OK;
 }
 
@@ -1604,7 +1815,11 @@ hmc_status hmc_time_kernels(hmc_ctx* x, int32_t reps, double* ms) {
         HMC_TRY(timed(2, [&] { return x->hip(hmc_launch_trunk_bwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, x->stream), "trunk_bwd"); }));
     }
     HMC_TRY(timed(3, [&] { return x->hip(hmc_launch_update(P, x->sa, UPD_GRAD, update_grid(x), x->upd_sub, x->stream), "update"); }));
-    // leave U consistent with the gradient just recomputed
+    // leave U consistent with the gradient just recomputed: BF16 and
+    // split-BF16 engines define U by the FP32 energy pass, whose likelihood
+    // partials still hold the end of the last trajectory (theta_L, also
+    // after a rejection), so it runs again at the current positions first
+    HMC_TRY(launch_energy(x, x->stream));
     HMC_HIP(x, hmc_launch_traj_end(P, x->sa, END_ENERGY, x->stream));
     HMC_HIP(x, hipStreamSynchronize(x->stream));
     return HMC_OK;

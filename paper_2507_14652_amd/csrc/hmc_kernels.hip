@@ -876,10 +876,15 @@ __device__ __forceinline__ void ulik_store(double* slot8, double v) {
 // layer from the top, the selected weight-gradient partials, then (while a
 // lower layer still has selected entries) the adjoint of the layer input.
 // m: the chain's tables (stage_meta, published); lowest: lowest_layer() of
-// the chain.  SQ: squared weight-gradient terms (sensitivity pass).
+// the chain; B: the tower's biases (staged).  SQ: squared weight-gradient
+// terms (sensitivity pass).  With tp.rc1 slab 1 shares its LDS with slab 3,
+// which the forward pass wrote later, so a_1 is recomputed from the input
+// (layer 0's tile product and tanh) once layer 2's adjoint no longer needs
+// slab 3.
 template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, const TileMeta* m, int t,
-                                               const typename PT<P>::T* W, typename PT<P>::T* sm, int lowest) {
+                                               const typename PT<P>::T* W, const typename PT<P>::A* B,
+                                               typename PT<P>::T* sm, int lowest) {
     typedef typename PT<P>::A A;
     const long long o = m->o;
     const int n = m->n;
@@ -889,6 +894,13 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     const int* bseg = m->bseg;
     const unsigned dmask = m->dmask;
     for (int l = tp.nl - 1; l >= lowest; --l) {
+        if (l == 1 && tp.rc1) {
+            // the barrier that ended layer 2's adjoint product has retired
+            // every read of slab 3 (delta_3)
+            EpiTanh<P> e{B + tp.bo[0], sm + tp.lo[1], tp.ls[1]};
+            gemm<P, R>(W + tp.wo[0], tp.wp[0], tp.wp[0], tp.wp[1], sm + tp.lo[0], tp.ls[0], e);
+            __syncthreads();
+        }
         if (dmask & (1u << l)) {
             dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
                                tp.wp[l + 1] >> 4, tp.wp[l] >> 4, a.mw + m->mwoff[l], seg[l], part);
@@ -1008,7 +1020,7 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
     ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * sq);
     if constexpr (!FWD) {
         __syncthreads();
-        tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
+        tower_backward<P, R>(a, tp, meta, t, W, B, sm, lowest);
     }
 }
 
@@ -1052,7 +1064,7 @@ __global__ __launch_bounds__(HMC_NT) void k_tower_sens(const GradArgs a, int tow
         so[r * tp.ls[L + 1] + col] = r < nv ? sv[col] : (T)0;
     }
     __syncthreads();
-    tower_backward<P, R, true>(a, tp, meta, t, W, sm, 0);
+    tower_backward<P, R, true>(a, tp, meta, t, W, B, sm, 0);
 }
 
 // Output of one tower at the current weights for the rows of its tile,
@@ -1145,125 +1157,6 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_predict(const GradArgs a, int c,
 }
 
 
-// Resident MLP kernel for networks whose weights fit in LDS beside the
-// activation slabs.  One workgroup per (chain, group of tpw row tiles):
-// the chain's weights are copied into LDS once (rows padded by 16 bytes, so
-// the 16 lanes of a fragment read hit distinct banks), then every tile runs
-// forward, FP64 head and adjoint from LDS.  Thread tid owns the selected
-// entries tid + 256 m (m < KPT) of its chain and sums their weight-gradient
-// terms over all its tiles in registers; one partial set per workgroup goes
-// to memory (the update kernel sums the groups in a fixed order).
-template <int P, int R, int KPT>
-__global__ __launch_bounds__(HMC_NT) void k_mlp_res(const GradArgs a) {
-    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* sm = reinterpret_cast<T*>(smem);
-    double* red = reinterpret_cast<double*>(smem + a.red_off);
-    int c, grp;
-    if (!tile_of(a.n_chains * a.groups, a.groups, c, grp)) return;
-    if (!a.active[c]) return;
-    const TowerPlan& tp = a.ta;
-    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* B = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
-    T* smw = sm + a.w_lds_off;
-    // weights -> LDS, row by row into the padded layout
-    {
-        constexpr int E = 16 / sizeof(T);
-        for (int l = 0; l < tp.nl; ++l) {
-            const int in = tp.wp[l], out = tp.wp[l + 1];
-            const int cw = in / E, ct = out / E;
-            for (int i = threadIdx.x; i < out * cw; i += blockDim.x) {
-                const int r = i / cw, q = i - r * cw;
-                *reinterpret_cast<uint4*>(smw + tp.lwo[l] + r * (in + E) + q * E) =
-                    *reinterpret_cast<const uint4*>(W + tp.wo[l] + (size_t)r * in + q * E);
-            }
-            for (int i = threadIdx.x; i < in * ct; i += blockDim.x) {
-                const int r = i / ct, q = i - r * ct;
-                *reinterpret_cast<uint4*>(smw + tp.lwto[l] + r * (out + E) + q * E) =
-                    *reinterpret_cast<const uint4*>(W + tp.wto[l] + (size_t)r * out + q * E);
-            }
-        }
-    }
-    // the entries this thread owns: code and layer
-    const long long o = a.offs[c];
-    const int n = (int)(a.offs[c + 1] - o);
-    const int* seg = a.seg + (size_t)c * a.nseg;
-    int code[KPT], lay[KPT];
-    A acc[KPT];
-#pragma unroll
-    for (int m = 0; m < KPT; ++m) {
-        const int k = threadIdx.x + m * HMC_NT;
-        acc[m] = (A)0;
-        lay[m] = -1;
-        code[m] = 0;
-        if (k < n) {
-            code[m] = a.ecode[o + k];
-            int l = 0;
-            while (l + 1 < tp.nl && k >= seg[l + 1]) ++l;
-            lay[m] = l;
-        }
-    }
-    int lowest = tp.nl;
-    for (int l = 0; l < tp.nl; ++l)
-        if (seg[l + 1] > seg[l]) { lowest = l; break; }
-    const int L = tp.nl - 1;
-    constexpr int E = 16 / sizeof(T);
-    double sq = 0.0;
-    for (int tt = 0; tt < a.tpw; ++tt) {
-        const int t = grp * a.tpw + tt;
-        if (t >= a.tiles_a) break;
-        __syncthreads();
-        load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0],
-                        tp.wp[0]);
-        __syncthreads();
-        for (int l = 0; l < L; ++l) {
-            EpiTanh<P> e{B + tp.bo[l], sm + tp.lo[l + 1], tp.ls[l + 1]};
-            gemm<P, R>(smw + tp.lwo[l], tp.wp[l] + E, tp.wp[l], tp.wp[l + 1], sm + tp.lo[l], tp.ls[l], e);
-            __syncthreads();
-        }
-        EpiMlpHead<P> h{B + tp.bo[L], sm + tp.lo[L + 1], tp.ls[L + 1], a.target + (size_t)t * R * a.d_out,
-                        a.d_out, t * R, a.n_rows_a,
-                        a.inv_lik_var, 0.0};
-        gemm<P, R>(smw + tp.lwo[L], tp.wp[L] + E, tp.wp[L], tp.wp[L + 1], sm + tp.lo[L], tp.ls[L], h);
-        sq += h.sq;
-        __syncthreads();
-        for (int l = L; l >= lowest; --l) {
-            const T* D = sm + tp.lo[l + 1];
-            const T* X = sm + tp.lo[l];
-            const int ld = tp.ls[l + 1], lx = tp.ls[l];
-#pragma unroll
-            for (int m = 0; m < KPT; ++m) {
-                if (lay[m] != l) continue;
-                const int i = code[m] >> 16, j = code[m] & 0xFFFF;
-                A s = (A)0;
-                if (j == 0xFFFF) {
-#pragma unroll 8
-                    for (int r = 0; r < R; ++r) s += ld1<P>(D + r * ld, i);
-                } else {
-#pragma unroll 8
-                    for (int r = 0; r < R; ++r) s = fma(ld1<P>(D + r * ld, i), ld1<P>(X + r * lx, j), s);
-                }
-                acc[m] += s;
-            }
-            if (l > lowest) {
-                __syncthreads();
-                EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};
-                gemm<P, R>(smw + tp.lwto[l], tp.wp[l + 1] + E, tp.wp[l + 1], tp.wp[l], sm + tp.lo[l + 1],
-                           tp.ls[l + 1], e);
-                __syncthreads();
-            }
-        }
-    }
-    A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)grp * n;
-#pragma unroll
-    for (int m = 0; m < KPT; ++m) {
-        const int k = threadIdx.x + m * HMC_NT;
-        if (k < n) part[k] = acc[m];
-    }
-    const double s = block_sum(sq, red);
-    if (threadIdx.x == 0) a.ulik[((size_t)c * a.groups + grp) * 8] = 0.5 * a.inv_lik_var * s;
-}
-
 // DeepONet trunk forward: T = trunk(y_q) for one (chain, query tile).
 template <int P, int R>
 __global__ __launch_bounds__(HMC_NT) void k_trunk_fwd(const GradArgs a) {
@@ -1342,7 +1235,7 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
     gemm<P, R>(ttc, a.nq_rows, a.nq_pad, pp, sm + a.dg_off, a.dg_ld, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
+    tower_backward<P, R>(a, tp, meta, t, W, B, sm, lowest);
 }
 
 // DeepONet trunk adjoint tile: recompute the trunk forward for the tile's
@@ -1411,14 +1304,14 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
     EpiStore<P> es{sm + tp.lo[L + 1], tp.ls[L + 1]};
     gemm<P, R>(btc, a.nu_cols, a.nu_cols, tp.wp[L + 1], X, ldx, es);
     __syncthreads();
-    tower_backward<P, R>(a, tp, meta, t, W, sm, lowest);
+    tower_backward<P, R>(a, tp, meta, t, W, B, sm, lowest);
 }
 
 // ---------------------------------------------------------------------------
 // Per-entry state kernels.
 
-// w32: also into the FP32 weight copy of the energy pass (when there is one).
-// d0, d1: the entry's destinations s.dst[2e], s.dst[2e + 1].
+// w32: also into the weight (and bias) shadows of the energy pass, when
+// there are any.  d0, d1: the entry's destinations s.dst[2e], s.dst[2e + 1].
 template <int P>
 __device__ __forceinline__ void scatter_to(const StateArgs& s, int c, int d0, int d1, typename PT<P>::S x,
                                            bool w32) {
@@ -1427,13 +1320,20 @@ __device__ __forceinline__ void scatter_to(const StateArgs& s, int c, int d0, in
         T* W = reinterpret_cast<T*>(s.wbuf) + c * s.wstride;   // rows of multiples of 32: flat indices
         st1<P>(W, d0, (A)x);
         st1<P>(W, d1, (A)x);
-        if (w32 && s.wbuf32) {   // FP32 shadow of the weights for the energy pass
-            float* W32 = reinterpret_cast<float*>(s.wbuf32) + c * s.wstride;
-            W32[d0] = (float)x;
-            W32[d1] = (float)x;
+        if (w32 && s.wbuf32) {   // the energy pass's weights: FP32 or FP64
+            if (s.w32_f64) {
+                double* W64 = reinterpret_cast<double*>(s.wbuf32) + c * s.wstride;
+                W64[d0] = (double)x;
+                W64[d1] = (double)x;
+            } else {
+                float* W32 = reinterpret_cast<float*>(s.wbuf32) + c * s.wstride;
+                W32[d0] = (float)x;
+                W32[d1] = (float)x;
+            }
         }
     } else {
         reinterpret_cast<A*>(s.bbuf)[c * s.bstride + (-d0 - 1)] = (A)x;
+        if (w32 && s.bbuf64) reinterpret_cast<double*>(s.bbuf64)[c * s.bstride + (-d0 - 1)] = (double)x;
     }
 }
 template <int P>
@@ -1665,6 +1565,35 @@ __global__ __launch_bounds__(256) void k_traj_end(const StateArgs s, int mode) {
         s.n_acc[c] += acc ? 1 : 0;
         s.n_div[c] += fin ? 0 : 1;
         s.iter[c] = it + 1;
+        const int adapt = *s.adapt_on;
+        if (adapt == 2) {
+            // calibration: count and sum of the acceptance probabilities
+            double* d = s.da + 4 * c;
+            d[0] += 1.0;
+            d[1] += fin ? fmin(1.0, exp(H0 - H1)) : 0.0;
+        } else if (adapt == 1) {
+            // Dual averaging of the step size toward a target acceptance
+            // statistic (Hoffman and Gelman 2014, HMC with dual averaging,
+            // the scheme Sec. 4.3 uses for its 80% runs): with alpha the
+            // Metropolis acceptance probability of this trajectory (0 when
+            // divergent), after iteration m
+            //   H-bar_m = (1 - 1/(m + t0)) H-bar_{m-1} + (target - alpha)/(m + t0)
+            //   log eps_{m+1} = mu - sqrt(m)/gamma * H-bar_m
+            //   log eps-bar_{m+1} = m^-kappa log eps_{m+1} + (1 - m^-kappa) log eps-bar_m
+            // and the next trajectory takes eps_{m+1}.
+            double* d = s.da + 4 * c;
+            const double target = s.da_cfg[0], gamma = s.da_cfg[1], t0 = s.da_cfg[2], kappa = s.da_cfg[3];
+            const double alpha = fin ? fmin(1.0, exp(H0 - H1)) : 0.0;
+            const double m = d[0] + 1.0;
+            const double w = 1.0 / (m + t0);
+            const double hbar = (1.0 - w) * d[1] + w * (target - alpha);
+            const double log_eps = d[3] - sqrt(m) / gamma * hbar;
+            const double eta = pow(m, -kappa);
+            d[0] = m;
+            d[1] = hbar;
+            d[2] = eta * log_eps + (1.0 - eta) * d[2];
+            s.eps[c] = exp(log_eps);
+        }
     }
 }
 
@@ -1759,16 +1688,14 @@ hipError_t set_lds(size_t lds) {
     if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_mlp_res<P, R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if constexpr (P < 2) {
         if ((e = hipFuncSetAttribute((const void*)k_tower_sens<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_tower_out<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_mlp_predict<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     }
-    if constexpr (P == 1) {
-        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
-        if ((e = hipFuncSetAttribute((const void*)k_branch_grad<1, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if constexpr (P < 2) {   // the energy passes (FP32 or FP64)
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     }
     return hipSuccess;
 }
@@ -1855,6 +1782,20 @@ hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int
     return hipGetLastError();
 }
 
+// Zero fill of n doubles (a kernel rather than a memset, so that callers
+// may capture it in a graph).
+__global__ __launch_bounds__(256) void k_zero_f64(double* p, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+hipError_t hmc_launch_zero(double* p, long long n, hipStream_t s) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(g), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s) {
     const unsigned g = (unsigned)((n + 255) / 256);
     if (g == 0) return hipSuccess;
@@ -1899,37 +1840,37 @@ hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int gri
 }
 
 // FP32 energy pass (forward and likelihood partials only).
-hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+// Energy passes (forward and likelihood partials only) in FP32 (P = 1) or
+// FP64 (P = 0).
+template <int P>
+hipError_t launch_energy_mlp(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     switch (R) {
-        case 16: hipLaunchKernelGGL((k_mlp_grad<1, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_mlp_grad<1, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
-        case 64: hipLaunchKernelGGL((k_mlp_grad<1, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_mlp_grad<P, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_mlp_grad<P, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_mlp_grad<P, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+template <int P>
+hipError_t launch_energy_branch(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
     switch (R) {
-        case 16: hipLaunchKernelGGL((k_branch_grad<1, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_branch_grad<1, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
-        case 64: hipLaunchKernelGGL((k_branch_grad<1, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_branch_grad<P, 16, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_branch_grad<P, 32, true>), dim3(grid), dim3(nt), lds, s, a); break;
+        case 64: hipLaunchKernelGGL((k_branch_grad<P, 64, true>), dim3(grid), dim3(nt), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-
-template <int P, int R, int KPT>
-hipError_t launch_res(const GradArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_mlp_res<P, R, KPT>), dim3(grid), dim3(HMC_NT), lds, s, a);
-    return hipGetLastError();
+hipError_t hmc_launch_mlp_energy(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    if (P == 0) return launch_energy_mlp<0>(R, nt, a, grid, lds, s);
+    if (P == 1) return launch_energy_mlp<1>(R, nt, a, grid, lds, s);
+    return hipErrorInvalidValue;
 }
-
-// Resident MLP kernel; kpt = selected entries per thread (4 or 8).
-hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
-#define C_(p, r)                                                                   \
-    return kpt <= 4 ? launch_res<p, r, 4>(a, grid, lds, s) : launch_res<p, r, 8>(a, grid, lds, s)
-    HMC_DISPATCH_PR(P, R, C_)
-#undef C_
+hipError_t hmc_launch_branch_energy(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    if (P == 0) return launch_energy_branch<0>(R, nt, a, grid, lds, s);
+    if (P == 1) return launch_energy_branch<1>(R, nt, a, grid, lds, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int sub, hipStream_t st) {

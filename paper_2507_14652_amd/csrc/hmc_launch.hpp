@@ -10,9 +10,8 @@ hipError_t hmc_launch_mlp_grad(int P, int R, int nt, const GradArgs& a, int grid
 hipError_t hmc_launch_trunk_fwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_branch_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_trunk_bwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_mlp_res(int P, int R, int kpt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_mlp_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t hmc_launch_branch_energy(int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_mlp_energy(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t hmc_launch_branch_energy(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t hmc_launch_tower_sens(int P, int R, int nt, const GradArgs& a, int tower, const void* seed, int grid,
                                  size_t lds, hipStream_t s);
 hipError_t hmc_launch_tower_out(int P, int R, int nt, const GradArgs& a, int tower, void* out, int ld, int grid,
@@ -24,6 +23,7 @@ hipError_t hmc_launch_mlp_predict(int P, int R, int nt, const GradArgs& a, int c
 hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int ld, int p, long long nu, long long nq,
                                      const void* b0, double* mean, double* m2, double* var, double inv_k,
                                      double inv_n, hipStream_t s);
+hipError_t hmc_launch_zero(double* p, long long n, hipStream_t s);
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int sub, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);

@@ -25,9 +25,10 @@ struct TowerPlan {
     long long wto[HMC_MAXL];    // offset of W_l^T
     long long bo[HMC_MAXL];     // offset of b_l in the per-chain bias buffer
     long long fo[HMC_MAXL];     // flat parameter index of W_l[0][0]
-    int lwo[HMC_MAXL];          // resident kernels: LDS offset (elements) of W_l, rows padded
-    int lwto[HMC_MAXL];         // resident kernels: LDS offset of W_l^T, rows padded
     int seg0;                   // first layer of this tower in the segment table
+    int rc1;                    // 1: slabs 1 and 3 share one LDS region (towers of 4 or more layers that
+                                //   do not fit otherwise); the adjoint pass recomputes a_1 from the
+                                //   input before layer 1's weight gradient, when slab 3 is no longer needed
 };
 
 // Per-chain mask tables of one tower, staged in LDS by the tile kernels
@@ -92,11 +93,6 @@ struct GradArgs {
     int dgt_stage;              // 1: the trunk adjoint tile stages its rows of dgt in LDS (at dgt_lds, row
     int dgt_lds, dgt_lds_ld;    //   stride dgt_lds_ld elements) before the product dT = dG^T B; 0: reads them
                                 //   from global memory
-    // Resident MLP kernel: weights held in LDS, several row tiles per
-    // workgroup, selected-entry partials accumulated in registers.
-    int w_lds_off;              // LDS offset (elements) of the weight copy
-    int tpw;                    // row tiles per workgroup
-    int groups;                 // workgroups per chain (partials per chain)
 };
 
 // Arguments of the per-entry kernels (reduction of partials, kicks, drifts,
@@ -124,10 +120,16 @@ struct StateArgs {
     const int* dst;             // [2 * nnz] scatter destinations
     void* wbuf;
     long long wstride;
-    void* wbuf32;               // FP32 shadow of wbuf (same offsets) or null
+    void* wbuf32;               // shadow of wbuf for the energy pass (same offsets) or null
+    int w32_f64;                // 1: that shadow holds doubles (FP64 energies), 0: floats
+    void* bbuf64;               // FP64 shadow of bbuf for FP64 energies, or null
     void* bbuf;
     long long bstride;
-    const double* eps;          // [C]
+    double* eps;                // [C] step sizes (written by the step-size adaptation)
+    double* da;                 // [C][4] dual-averaging state: iterations m, H-bar, log eps-bar, mu
+                                //   (calibration: count and sum of the acceptance probabilities)
+    const int* adapt_on;        // device flag: 1 while the step sizes adapt, 2 while acceptance is summed
+    const double* da_cfg;       // [4] target acceptance, gamma, t0, kappa
     double inv_prior_var;
     double* U;                  // [C]
     double* U_save;             // [C]

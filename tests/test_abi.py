@@ -3,6 +3,7 @@ declares, and rejects invalid arguments on the host before any device work
 (these calls never reach the GPU)."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -100,6 +101,7 @@ def test_calls_on_a_null_engine_are_rejected():
     lib = binding.load()
     assert lib.hmc_sync(None) == binding.HMC_EINVAL
     assert lib.hmc_grad(None, None, None) == binding.HMC_EINVAL
+    assert lib.hmc_adapt(None, 1, None, 1, 0.8, None) == binding.HMC_EINVAL
     lib.hmc_destroy(None)
 
 
@@ -179,3 +181,36 @@ def test_autotune_rejects_bad_arguments_on_the_host():
     assert lib.hmc_autotune(ctypes.byref(net), ctypes.byref(mask), ctypes.byref(data), 3, ctypes.byref(best),
                             None) == binding.HMC_EINVAL
     assert "lik_sd" in lib.hmc_last_error(None).decode()
+
+
+@needs_lib
+def test_trajectory_length_matches_the_oracle():
+    """hmc_trajectory_length (host code in the library) against the oracle's
+    rule on the App. C cases and on vectors of variances, both modes."""
+    import json
+    from oracle import hmc as oh
+    from paper_2507_14652_amd import trajectory_length
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "appc_trajectory_lengths.json")))
+    for case in d["cases"]:
+        assert trajectory_length([case["posterior_variance"]], case["step_size"]) == case["L"]
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        v = rng.uniform(0, 1, rng.integers(1, 9)) ** 3
+        e = 10 ** rng.uniform(-4, -1)
+        for mode in ("max", "median"):
+            if math.pi * (v.max() if mode == "max" else np.median(v)) / (2 * e) > 1e6:
+                continue
+            assert trajectory_length(v, e, mode) == oh.trajectory_length(v, e, mode)
+
+
+@needs_lib
+@pytest.mark.parametrize("var,eps,mode", [([], 1e-3, 1), ([0.1], 0.0, 1), ([0.1], 1e-3, 2), ([-0.1], 1e-3, 0),
+                                          ([float("nan")], 1e-3, 0), ([1e6], 1e-6, 0)])
+def test_trajectory_length_rejects_bad_input(var, eps, mode):
+    lib = binding.load()
+    v = np.array(var if var else [0.0], dtype=np.float64)
+    L = ctypes.c_int32(-7)
+    st = lib.hmc_trajectory_length(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(var), mode, eps,
+                                   ctypes.byref(L))
+    assert st == binding.HMC_EINVAL and L.value == -7
+    assert lib.hmc_last_error(None)

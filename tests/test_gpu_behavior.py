@@ -296,3 +296,30 @@ def test_energy_copy_holds_the_end_positions(name, kw, L, prec):
         print(f"{name} {prec} L={L} chain {c}: H1 {H1[c]:.12e}, U(theta_L) + K {U[c] + K:.12e}")
         assert abs(H1[c] - (U[c] + K)) <= 1e-12 * abs(H1[c])
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("name,kw", [("uneven_mlp_bf16", dict(n_rows=150, n_chains=2)),
+                                     ("antideriv_deeponet_bf16", dict(n_u=45, n_q=17, n_chains=2))])
+def test_kernel_timing_leaves_the_state_alone(name, kw, prec):
+    """hmc_time_kernels after a rejected trajectory: BF16 and split-BF16
+    engines define U by the FP32 energy pass, whose partials then hold the
+    rejected end point; the hook must leave positions, gradient and U of
+    every chain exactly as they were, and the next trajectory's H0 must use
+    that U."""
+    w = workloads.make(name, **kw)
+    s = _Sampler().from_workload(w, precision=prec, seed=3)
+    s.sample(2, w.eps, 5)
+    st = s.leapfrog(1e3, 4)                              # far too large: rejected
+    assert np.all(st["accepted"] == 0)
+    th0, U0, _ = s.get_state()
+    th0 = th0.clone()
+    s.time_kernels(3)
+    th1, U1, _ = s.get_state()
+    assert torch.equal(th0, th1)
+    np.testing.assert_array_equal(U0, U1)
+    # H0 of the next trajectory starts from that U
+    p0 = np.zeros(w.nnz, dtype=np.float32)
+    _, _, H0, _ = s.trajectory(p0, w.eps, 1)
+    np.testing.assert_array_equal(H0, U0)
+    s.close()

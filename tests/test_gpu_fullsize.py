@@ -5,9 +5,9 @@ chains that the oracle evaluates one by one.
 FP32 runs are held to 1e-5 relative (gradients norm-wise, positions in the
 infinity norm); BF16 runs, which have no exact reference (parity unpinned),
 to the measured bound stated below.  The operator-surrogate DeepONet
-(512-wide towers) runs only in BF16: in FP32 its activation slabs exceed the
-LDS of one workgroup even at 16 rows, which the engine reports as
-unsupported (checked below).
+(512-wide towers) fits one workgroup's LDS in FP32 and split BF16 only with
+its first and third activation slabs shared (the first recomputed in the
+adjoint pass); it is checked in those precisions at full size too.
 """
 
 import numpy as np
@@ -73,12 +73,13 @@ def test_full_size_gradient_bf16(name, chains):
     _check_grads(w, "bf16", chains, BF16_BOUND, ubound=1e-5)   # U from the FP32 energy pass
 
 
-def test_full_size_fp32_surface_deeponet_is_reported_unsupported():
-    from paper_2507_14652_amd.binding import HMCError, HMC_EUNSUPPORTED
-    w = workloads.make("surface_deeponet_bf16", n_chains=1)
-    with pytest.raises(HMCError) as e:
-        _sampler(w, precision="fp32")
-    assert e.value.status == HMC_EUNSUPPORTED
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_full_size_surface_deeponet_with_recompute(prec, bound):
+    """The operator surrogate (2048 conditions x 512 points, 512-wide towers)
+    in FP32 and split BF16: the engine shares slabs 1 and 3 of the towers
+    and recomputes the first hidden activation in the adjoint pass."""
+    w = workloads.make("surface_deeponet_bf16")
+    _check_grads(w, prec, [0, 31], bound, ubound=1e-5)
 
 
 def test_full_size_bench_trajectory():

@@ -70,6 +70,7 @@ class Workload:
     yq: Optional[np.ndarray] = None   # DeepONet trunk inputs  [n_q, d_y]
     v: Optional[np.ndarray] = None    # DeepONet targets [n_u, n_q]
     note: str = ""
+    energy: str = "default"   # forward pass behind U in the Hamiltonian: "default" or "fp64"
 
     @property
     def n_params(self) -> int:
@@ -242,4 +243,5 @@ def make(name: str, *, n_rows: Optional[int] = None, n_u: Optional[int] = None,
     offs, idx, th = _chains(master, theta0, [m] * C, 0.01)
     return Workload(name, "deeponet", wa, wb, precision or "bf16", 0.01, 5e-3, 1e-5, 50, C, 20,
                     theta0, offs, idx, th, u=c_in, yq=yq, v=v,
-                    note="8 upstream scalars ~U(0,1), 32x16 surface grid, smooth synthetic field")
+                    note="8 upstream scalars ~U(0,1), 32x16 surface grid, smooth synthetic field",
+                    energy="fp64")
