@@ -313,6 +313,20 @@ hmc_status hmc_sensitivity(const hmc_net_desc* net, const hmc_data_desc* data, c
 hmc_status hmc_predict(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t n_samples,
                        const hmc_data_desc* inputs, double* mean, double* var);
 
+/* hmc_predict for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and errors, but the call's device
+ * buffers (the tiled new inputs, the staged sample, the FP64 moments and the
+ * DeepONet tower outputs) come from a fixed 64 MiB region that the library
+ * holds on every GPU it runs on, and the call makes no device allocation.
+ * A request that needs more than 64 MiB of it (each buffer rounded up to 256
+ * bytes) returns HMC_EUNSUPPORTED before any device work.  Every call on one
+ * GPU uses the same region: calls that overlap on one GPU (from several
+ * threads, or engines on different streams) race and must be serialised by
+ * the caller; each call clears what it needs. */
+hmc_status hmc_predict_noalloc(hmc_ctx* ctx, int32_t chain, const void* samples, int64_t n_samples,
+                               const hmc_data_desc* inputs, double* mean, double* var);
+
 /* The sensitive subset of Sec. 3.1 (threshold equation): the parameters
  * ordered from the most to the least sensitive (equal values in index
  * order), and the largest count N whose cumulative share of sum(s2) is at

@@ -27,7 +27,7 @@ ABI_FUNCTIONS = (
     "hmc_init", "hmc_leapfrog", "hmc_sample", "hmc_grad", "hmc_trajectory", "hmc_momentum",
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
     "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
-    "hmc_predict", "hmc_init_tuned", "hmc_autotune", "hmc_adapt", "hmc_trajectory_length",
+    "hmc_predict", "hmc_init_tuned", "hmc_autotune", "hmc_adapt", "hmc_trajectory_length", "hmc_predict_noalloc",
     "hmc_calibrate",
 )
 
@@ -102,6 +102,7 @@ def load():
         "hmc_sensitivity": [POINTER(NetDesc), POINTER(DataDesc), POINTER(c_double), POINTER(c_double), P],
         "hmc_select_mask": [POINTER(c_double), c_int64, c_double, POINTER(c_int64), POINTER(c_int64)],
         "hmc_predict": [P, c_int32, P, c_int64, POINTER(DataDesc), POINTER(c_double), POINTER(c_double)],
+        "hmc_predict_noalloc": [P, c_int32, P, c_int64, POINTER(DataDesc), POINTER(c_double), POINTER(c_double)],
         "hmc_init_tuned": [POINTER(c_void_p), POINTER(NetDesc), POINTER(MaskDesc), POINTER(DataDesc), c_uint64, P,
                            POINTER(Tuning)],
         "hmc_autotune": [POINTER(NetDesc), POINTER(MaskDesc), POINTER(DataDesc), c_int32, POINTER(Tuning),
@@ -405,11 +406,12 @@ class Sampler:
                                            d.ctypes.data_as(POINTER(c_int64))))
         return a, d
 
-    def predict(self, samples, x=None, chain=0, u=None, yq=None):
+    def predict(self, samples, x=None, chain=0, u=None, yq=None, no_alloc=False):
         """Mean and variance (FP64 arrays) of the network output over stored
         samples ([n][nnz], as sample() writes them; torch tensor or NumPy
         array) of one chain: an MLP at the rows of x ([rows][d_out]), a
-        DeepONet at functions u and query points yq ([n_u][n_q])."""
+        DeepONet at functions u and query points yq ([n_u][n_q]).
+        no_alloc: hmc_predict_noalloc (the library's fixed device scratch)."""
         if isinstance(samples, torch.Tensor):
             if samples.dtype != self.state_dtype or samples.dim() != 2 or samples.shape[1] != self.nnz:
                 raise ValueError("samples must be [n][nnz] in the state dtype")
@@ -430,7 +432,8 @@ class Sampler:
         mean = np.empty(shape)
         var = np.empty(shape)
         torch.cuda.synchronize()
-        self._check(self._lib.hmc_predict(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]), ctypes.byref(data),
+        fn = self._lib.hmc_predict_noalloc if no_alloc else self._lib.hmc_predict
+        self._check(fn(self._ctx, int(chain), _ptr_of(samples), int(samples.shape[0]), ctypes.byref(data),
                        _dptr(mean), _dptr(var)))
         del keep
         return mean, var

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,9 +16,40 @@
 #include "hmc_launch.hpp"
 #include "hmc_plan.hpp"
 
+// Fixed device scratch of hmc_predict_noalloc: one copy on every GPU the
+// library runs on, held until the process ends.  Host code never uses this
+// name as an address (on the host it is a stand-in); it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+#define HMC_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) unsigned char scratch[HMC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+// Device address of `scratch` per device, looked up once per device by the
+// first hmc_init that runs with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+void scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[dev] = p;
+    else g_scratch_err[dev] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+void* scratch_of(int dev, hipError_t* err) {
+    if (dev < 0 || dev >= kMaxDevices) { *err = hipErrorInvalidDevice; return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
 
 size_t g_lds_cap = 160 * 1024;   // LDS per workgroup on gfx950; replaced by the device's value
 
@@ -1057,6 +1089,7 @@ hmc_status init_ctx(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
         }
     }
     hipError_t e = hipGetDevice(&x->device);
+    if (e == hipSuccess) scratch_setup(x->device);   // with the engine's device current
     if (e == hipSuccess) {
         if (hip_stream) x->stream = (hipStream_t)hip_stream;
         else {
@@ -1465,6 +1498,20 @@ hmc_status hmc_predict(hmc_ctx* x, int32_t chain, const void* samples, int64_t n
                        const hmc_data_desc* inputs, double* mean, double* var) {
     if (!x) return HMC_EINVAL;
     PredictBuffers buf;
+    return predict_impl(x, chain, samples, n_samples, inputs, mean, var, buf);
+}
+
+hmc_status hmc_predict_noalloc(hmc_ctx* x, int32_t chain, const void* samples, int64_t n_samples,
+                               const hmc_data_desc* inputs, double* mean, double* var) {
+    if (!x) return HMC_EINVAL;
+    hipError_t err = hipSuccess;
+    void* p = scratch_of(x->device, &err);
+    if (!p)
+        return x->fail(HMC_EDEVICE, std::string("the fixed device scratch has no address on this device: ") +
+                                        hipGetErrorString(err));
+    PredictBuffers buf;
+    buf.region = (char*)p;
+    buf.cap = HMC_SCRATCH_BYTES;
     return predict_impl(x, chain, samples, n_samples, inputs, mean, var, buf);
 }
 
