@@ -593,11 +593,16 @@ def main():
     import workloads
     from paper_2507_14652_amd import Sampler, autotune_workload
 
+    def progress(msg):
+        print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
     w = workloads.make(args.config)
     if args.precision:
         w = dataclasses.replace(w, precision=args.precision)
+    progress(f"{w.name}: {w.precision}, {w.n_chains} chains, L={w.L}")
     tuning = autotune_workload(w, reps=10)[0] if args.autotune else None
     s = Sampler.from_workload(w, seed=2507, tuning=tuning)
+    progress(f"engine ready ({s.info['device_bytes'] / 2**30:.2f} GiB on the device)")
     C, L = w.n_chains, w.L
     st_dtype = torch.float64 if w.precision == "fp64" else torch.float32
     out = torch.empty((args.steps, w.nnz), dtype=st_dtype, device="cuda")
@@ -605,9 +610,11 @@ def main():
     # untimed: per-chain step sizes by dual averaging to 80% acceptance, then
     # the warm-up iterations at those step sizes
     eps_c = s.adapt(args.adapt, w.eps, L) if args.adapt else np.full(C, w.eps)
+    progress(f"step sizes adapted over {args.adapt} iterations: median {np.median(eps_c):.3e}")
     if args.warmup:
         s.sample(args.warmup, eps_c, L, out=warm)
     torch.cuda.synchronize()
+    progress(f"{args.warmup} warm-up iterations done; timing {args.steps}")
     t0 = time.perf_counter()
     _, stats = s.sample(args.steps, eps_c, L, out=out)
     torch.cuda.synchronize()
@@ -658,10 +665,13 @@ def main():
         "gradient_roofline": gradient,
     }
     s.close()
+    progress(f"timed: {line['value']:.1f} {line['unit']}, acceptance {acc:.3f}")
     if not args.no_ess and w.kind == "mlp":
         line["ess"] = ess_comparison(w, seed=2507, budget_s=args.ess_budget)
+        progress("ESS comparison done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        progress("CPU baseline done")
     print(json.dumps(line))
 
 

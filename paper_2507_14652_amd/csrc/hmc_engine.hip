@@ -351,34 +351,66 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row, size_t 
 // fewer workgroups than the 256 compute units (smaller tiles re-read the
 // weights more often, so a grid of one 512-thread workgroup per compute unit
 // is enough: the DeepONet trunk adjoint runs 50 -> 46 us at 32 rows instead
-// of 16).  A tuning value (16, 32 or 64; 0 when it does not fit) or else
-// HMC_ROWS_A / HMC_ROWS_B overrides it.
-// fixed: bytes beside the slabs (staged biases, alignment).
-// A tower that fits at no tile height with all its slabs shares slabs 1 and
-// 3 (alias, recomputing a_1 in the adjoint pass: one tile product of the
-// narrow input layer) when it has four or more layers.
+// of 16).  A tower of four or more layers shares slabs 1 and 3 (alias,
+// recomputing a_1 in the adjoint pass: one tile product of the narrow input
+// layer) where that makes a taller tile fit.  A tuning value (16, 32 or 64;
+// 0 when it does not fit) or else HMC_ROWS_A / HMC_ROWS_B overrides the
+// height.  fixed: bytes beside the slabs (staged biases, alignment);
+// scr_bytes: the dense weight-gradient scratch, needed at tile heights that
+// are multiples of kch.
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
-              const char* env, int forced, bool& alias) {
+              const char* env, int forced, size_t scr_bytes, int kch, bool& alias) {
     alias = false;
-    auto fits = [&](int r) {
-        return tower_lds(w, prec, r, alias) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed <= g_lds_cap;
+    auto fits_as = [&](int r, bool al) {
+        const size_t scr = r % kch == 0 ? scr_bytes : 0;
+        return tower_lds(w, prec, r, al) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed + scr <= g_lds_cap;
     };
-    auto any_fits = [&]() { return fits(16) || fits(32) || fits(64); };
     const char* rc = std::getenv("HMC_RECOMPUTE");   // "1": share wherever possible (tests)
-    if (can_alias(w) && ((rc && !std::strcmp(rc, "1")) || !any_fits())) {
-        alias = true;
-        if (!any_fits()) alias = false;
-    }
-    if (forced) return fits(forced) ? forced : 0;
+    const bool force_alias = can_alias(w) && rc && !std::strcmp(rc, "1");
+    // the sharing choice for one candidate height; false: it does not fit
+    auto choose = [&](int r, bool& al) {
+        if (force_alias) { al = true; return fits_as(r, true); }
+        if (fits_as(r, false)) { al = false; return true; }
+        if (can_alias(w) && fits_as(r, true)) { al = true; return true; }
+        return false;
+    };
+    if (forced) return choose(forced, alias) ? forced : 0;
     if (const char* s = std::getenv(env)) {
         const int r = std::atoi(s);
-        if ((r == 16 || r == 32 || r == 64) && fits(r)) return r;
+        if ((r == 16 || r == 32 || r == 64) && choose(r, alias)) return r;
     }
     int best = 0;
     for (int R : {64, 32, 16})
-        if (fits(R)) { best = R; break; }
-    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 256 && fits(best / 2)) best /= 2;
+        if (choose(R, alias)) { best = R; break; }
+    bool al2 = false;
+    while (best > 16 && (long long)chains * ((rows + best - 1) / best) < 256 && choose(best / 2, al2)) {
+        best /= 2;
+        alias = al2;
+    }
     return best;
+}
+
+// Whether a tower may take the dense weight-gradient product on some layer
+// (so that its kernels need the per-wave scratch): BF16 and split-BF16
+// layers at least 64 wide on both sides, or any layer when dense is forced.
+bool dense_possible(const std::vector<int>& w, int prec, bool forced) {
+    if (forced) return true;
+    if (prec != HMC_BF16 && prec != HMC_BF16X3) return false;
+    for (size_t l = 0; l + 1 < w.size(); ++l)
+        if (w[l] >= 64 && w[l + 1] >= 64) return true;
+    return false;
+}
+
+// Dense weight-gradient unit of a layer (the selection lists are laid out
+// for it): P >= 2 with enough 4 x 2 units for every wave takes 4 x 2 blocks
+// (interleaved for BF16 with whole 64 x 32 units and no squared terms),
+// otherwise 2 x 2.  NI, NJ: padded output and input widths in 16-blocks.
+int dw_variant(int prec, int NI, int NJ, int nwave, bool sq) {
+    if (prec >= HMC_BF16 && (NI / 4) * ((NJ + 1) / 2) >= nwave) {
+        if (prec == HMC_BF16 && !sq && NI % 4 == 0 && NJ % 2 == 0) return DWV_IL;
+        return DWV_4X2;
+    }
+    return DWV_2X2;
 }
 
 hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
@@ -480,21 +512,33 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     const int la = (int)x->A.w.size() - 1;
     const int lb = x->kind == HMC_DEEPONET ? (int)x->B.w.size() - 1 : 0;
 
+    // Masked dW path overrides (tuning record, else HMC_DW) and the per-wave
+    // scratch of the dense weight-gradient product, reserved for towers
+    // that may take it.
+    const char* dwenv = std::getenv("HMC_DW");
+    const bool force_dense = x->tune.dw == 2 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "dense"));
+    const bool force_gather = x->tune.dw == 1 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "gather"));
+    const size_t scr_wg = (size_t)(pick_threads(0, x->tune.threads) / 64) * 4096;
+    const size_t scr_a = !force_gather && dense_possible(x->A.w, prec, force_dense || x->force_dense) ? scr_wg : 0;
+    const size_t scr_b = x->kind == HMC_DEEPONET && !force_gather &&
+                                 dense_possible(x->B.w, prec, force_dense || x->force_dense) ? scr_wg : 0;
+    const int kch = pad_of(prec);
+
     // Row tiles.
     long long rows_a, rows_b = 0;
     int nq_pad = 0;
     if (x->kind == HMC_MLP) {
         rows_a = data->n_rows;
         x->Ra = pick_rows(x->A.w, prec, (size_t)x->A.w.back() * 8, bias_bytes(x->A.w, prec, as), rows_a, x->C,
-                          "HMC_ROWS_A", x->tune.rows_a, x->alias_a);
+                          "HMC_ROWS_A", x->tune.rows_a, scr_a, kch, x->alias_a);
     } else {
         rows_a = data->n_u;
         rows_b = data->n_q;
         nq_pad = roundup((int)rows_b, pad);
         x->Ra = pick_rows(x->A.w, prec, (size_t)(nq_pad + lpad_of(prec)) * ts, bias_bytes(x->A.w, prec, as), rows_a,
-                          x->C, "HMC_ROWS_A", x->tune.rows_a, x->alias_a);
+                          x->C, "HMC_ROWS_A", x->tune.rows_a, scr_a, kch, x->alias_a);
         x->Rb = pick_rows(x->B.w, prec, 0, bias_bytes(x->B.w, prec, as), rows_b, x->C, "HMC_ROWS_B", x->tune.rows_b,
-                          x->alias_b);
+                          scr_b, kch, x->alias_b);
         if (!x->Rb)
             return x->fail(HMC_EUNSUPPORTED, x->tune.rows_b ? "trunk tower does not fit in LDS at the requested rows per tile"
                                                             : "trunk tower does not fit in LDS");
@@ -629,6 +673,11 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     x->lds_a += bias_bytes(x->A.w, prec, as);
     g.y_lds = (int)x->lds_a;
     if (x->kind == HMC_MLP) x->lds_a += (size_t)x->Ra * x->A.w.back() * 8;
+    if (scr_a && x->Ra % kch == 0) {
+        x->lds_a = (x->lds_a + 255) / 256 * 256;
+        g.ta.scr = (int)x->lds_a;
+        x->lds_a += scr_a;
+    }
     // The per-kernel limit is set to the device capacity (not this engine's
     // size) so that engines of different shapes in one process coexist.
     HMC_HIP(x, hmc_set_lds_limit(prec, x->Ra, g_lds_cap));
@@ -639,6 +688,11 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         x->lds_b += HMC_META_BYTES;
         g.bias_lds_b = (int)x->lds_b;
         x->lds_b += bias_bytes(x->B.w, prec, as);
+        if (scr_b && x->Rb % kch == 0) {
+            x->lds_b = (x->lds_b + 255) / 256 * 256;
+            g.tb.scr = (int)x->lds_b;
+            x->lds_b += scr_b;
+        }
         // the trunk adjoint tile's rows of the transposed output adjoint (the
         // operand of dT = dG^T B, reduced over all nu_cols functions) staged
         // in LDS when they fit beside the tower: one bulk load, issued at
@@ -726,10 +780,6 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     // dense product supports (tile rows a multiple of the MFMA K chunk).
     const int nlt = la + lb;
     std::vector<int> bseg((size_t)x->C * std::max(nlt, 1)), dflag((size_t)x->C * std::max(nlt, 1));
-    const char* dwenv = std::getenv("HMC_DW");
-    const bool force_dense = x->tune.dw == 2 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "dense"));
-    const bool force_gather = x->tune.dw == 1 || (x->tune.dw == 0 && dwenv && !std::strcmp(dwenv, "gather"));
-    const int kch = pad_of(prec);
     const long long DWK = 2;   // BF16: dense when density * R >= DWK
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
@@ -751,12 +801,21 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
             dflag[(size_t)c * nlt + L] = dense ? 1 : 0;
         }
     }
-    // Selection bitmaps of the dense layers: for row i of W_l and columns
-    // 32w .. 32w + 31, the bits of the selected columns and the number of
-    // selected weights of the layer before that word.  Chains with the same
-    // mask share one bitmap per layer.
-    std::vector<long long> mw_off((size_t)x->C * std::max(nlt, 1), -1);
-    std::vector<int2> mw_h;
+    // Selection lists of the dense layers.  Per (tower, layer) the unit
+    // variant (dw_variant) fixes which lane holds each dW[i][j] of a unit;
+    // per (chain, layer) a block of 32-bit words: for every unit half
+    // h = 2 u + bj the start of its entries (2 * units + 1 offsets, padded
+    // to an even count), then the entries (entry offset from the layer's
+    // first entry, LDS scratch slot (bi * 64 + 16 g + li) * 4 + v) of each
+    // half in CSR order.  Chains with the same mask share one block.
+    for (int L = 0; L < nlt; ++L) {
+        TowerPlan& tp = L < la ? g.ta : g.tb;
+        const int l = L < la ? L : L - la;
+        const int nt = L < la ? x->nt_a : x->nt_b;
+        tp.dwv[l] = dw_variant(prec, tp.wp[l + 1] >> 4, tp.wp[l] >> 4, nt / 64, x->force_dense);
+    }
+    std::vector<long long> ml_off((size_t)x->C * std::max(nlt, 1), -1);
+    std::vector<unsigned> ml_h;
     std::vector<int> distinct;   // first chain of each distinct mask
     for (int c = 0; c < x->C; ++c) {
         const long long o = x->offs[c], n = x->offs[c + 1] - o;
@@ -769,46 +828,69 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         for (int L = 0; L < nlt; ++L) {
             if (!dflag[(size_t)c * nlt + L]) continue;
             if (same >= 0 && dflag[(size_t)same * nlt + L]) {
-                mw_off[(size_t)c * nlt + L] = mw_off[(size_t)same * nlt + L];
+                ml_off[(size_t)c * nlt + L] = ml_off[(size_t)same * nlt + L];
                 continue;
             }
             const TowerPlan& tp = *lplan[L];
             const int l = lidx[L];
-            const int in = tp.w[l], out = tp.w[l + 1];
-            const int nwr = (in + 31) / 32;
-            const long long base = (long long)mw_h.size();
-            mw_off[(size_t)c * nlt + L] = base;
-            mw_h.resize(mw_h.size() + (size_t)out * nwr, int2{0, 0});
+            if (tp.scr == 0) return x->fail(HMC_EUNSUPPORTED, "internal: dense weight gradient without its LDS scratch");
+            const int in = tp.w[l];
+            const int NI = tp.wp[l + 1] >> 4, NJ = tp.wp[l] >> 4, var = tp.dwv[l];
+            const int BI = var == DWV_2X2 ? 2 : 4;
+            const int UI = var == DWV_IL ? NI / 4 : (NI + BI - 1) / BI;
+            const int UJ = var == DWV_IL ? NJ / 2 : (NJ + 1) / 2;
+            const int nh = 2 * UI * UJ, tabw = (nh + 2) & ~1;
             const int k0 = seg[(size_t)c * nseg + L], k1 = bseg[(size_t)c * nlt + L];
+            // unit half and scratch slot of every selected weight, in CSR order
+            std::vector<int> hof(k1 - k0), slot(k1 - k0), cnt(nh + 1, 0);
             for (int k = k0; k < k1; ++k) {
                 const long long off = mask->idx[o + k] - lstart[L];
                 const int i = (int)(off / in), j = (int)(off % in);
-                mw_h[(size_t)(base + (long long)i * nwr + j / 32)].x |= (int)(1u << (j % 32));
+                int u, bj, bi, g4, li, v;
+                if (var == DWV_IL) {
+                    const int ri = i % 64, cj = j % 32;
+                    u = (i / 64) * UJ + j / 32;
+                    g4 = ri / 16; v = (ri % 16) / 4; bi = ri % 4;
+                    li = cj / 2; bj = cj % 2;
+                } else {
+                    const int ri = i % (BI * 16), cj = j % 32;
+                    u = (i / (BI * 16)) * UJ + j / 32;
+                    bi = ri / 16; g4 = (ri % 16) / 4; v = ri % 4;
+                    bj = cj / 16; li = cj % 16;
+                }
+                hof[k - k0] = 2 * u + bj;
+                slot[k - k0] = (bi * 64 + 16 * g4 + li) * 4 + v;
+                ++cnt[2 * u + bj + 1];
             }
-            int cnt = 0;
-            for (long long q = 0; q < (long long)out * nwr; ++q) {
-                int2& e = mw_h[(size_t)(base + q)];
-                e.y = cnt;
-                cnt += __builtin_popcount((unsigned)e.x);
+            for (int h = 0; h < nh; ++h) cnt[h + 1] += cnt[h];
+            const long long base = (long long)ml_h.size();
+            ml_off[(size_t)c * nlt + L] = base;
+            ml_h.resize(ml_h.size() + (size_t)tabw + 2 * (size_t)(k1 - k0), 0u);
+            for (int h = 0; h <= nh; ++h) ml_h[(size_t)(base + h)] = (unsigned)cnt[h];
+            std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+            for (int k = k0; k < k1; ++k) {
+                const long long e = base + tabw + 2LL * fill[hof[k - k0]]++;
+                ml_h[(size_t)e] = (unsigned)(k - k0);
+                ml_h[(size_t)e + 1] = (unsigned)slot[k - k0];
             }
         }
     }
-    if (mw_h.size() > (size_t)INT32_MAX)
-        return x->fail(HMC_EUNSUPPORTED, "selection bitmaps exceed 2^31 words");
+    if (ml_h.size() > (size_t)INT32_MAX)
+        return x->fail(HMC_EUNSUPPORTED, "selection lists exceed 2^31 words");
     int* bseg_d = (int*)x->dalloc(sizeof(int) * bseg.size());
     int* dflag_d = (int*)x->dalloc(sizeof(int) * dflag.size());
-    int2* mw_d = (int2*)x->dalloc(sizeof(int2) * std::max<size_t>(mw_h.size(), 1));
-    long long* mwoff_d = (long long*)x->dalloc(sizeof(long long) * mw_off.size());
-    if (!bseg_d || !dflag_d || !mw_d || !mwoff_d) return x->fail(HMC_ENOMEM, "device allocation of the selection bitmaps failed");
+    unsigned* ml_d = (unsigned*)x->dalloc(sizeof(unsigned) * std::max<size_t>(ml_h.size(), 2));
+    long long* mloff_d = (long long*)x->dalloc(sizeof(long long) * ml_off.size());
+    if (!bseg_d || !dflag_d || !ml_d || !mloff_d) return x->fail(HMC_ENOMEM, "device allocation of the selection lists failed");
     HMC_HIP(x, hipMemcpy(bseg_d, bseg.data(), sizeof(int) * bseg.size(), hipMemcpyHostToDevice));
     HMC_HIP(x, hipMemcpy(dflag_d, dflag.data(), sizeof(int) * dflag.size(), hipMemcpyHostToDevice));
-    if (!mw_h.empty()) HMC_HIP(x, hipMemcpy(mw_d, mw_h.data(), sizeof(int2) * mw_h.size(), hipMemcpyHostToDevice));
-    HMC_HIP(x, hipMemcpy(mwoff_d, mw_off.data(), sizeof(long long) * mw_off.size(), hipMemcpyHostToDevice));
+    if (!ml_h.empty()) HMC_HIP(x, hipMemcpy(ml_d, ml_h.data(), sizeof(unsigned) * ml_h.size(), hipMemcpyHostToDevice));
+    HMC_HIP(x, hipMemcpy(mloff_d, ml_off.data(), sizeof(long long) * ml_off.size(), hipMemcpyHostToDevice));
     g.bseg = bseg_d;
     g.dflag = dflag_d;
     g.nl_total = nlt;
-    g.mw = mw_d;
-    g.mw_off = mwoff_d;
+    g.ml = ml_d;
+    g.ml_off = mloff_d;
     x->dense_layers = (int)std::count(dflag.begin(), dflag.end(), 1);
 
     long long* offs_d = (long long*)x->dalloc(sizeof(long long) * (x->C + 1));

@@ -628,56 +628,94 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
     if (e < n && sub == 0) part[k0 + e] = s;
 }
 
+// Selection-list entries of one dense weight-gradient unit, loaded before
+// its product so that their latency overlaps the MFMAs: the unit halves'
+// entry ranges and each lane's first DWP entries of each half.
+constexpr int DWP = 4;
+struct DwPre {
+    int e0[2], e1[2];
+    uint2 en[2][DWP];
+};
+__device__ __forceinline__ DwPre dw_prefetch(const unsigned* __restrict__ tab, const uint2* __restrict__ ent, int u) {
+    const int lane = threadIdx.x & 63;
+    DwPre p;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        p.e0[bj] = (int)tab[2 * u + bj];
+        p.e1[bj] = (int)tab[2 * u + bj + 1];
+#pragma unroll
+        for (int q = 0; q < DWP; ++q) {
+            const int e = p.e0[bj] + lane + 64 * q;
+            p.en[bj][q] = e < p.e1[bj] ? ent[e] : make_uint2(0u, 0u);
+        }
+    }
+    return p;
+}
+
+// Selected entries of a dense weight-gradient unit (BI x 2 blocks of 16 x 16
+// accumulators per lane: acc[bi][bj][v]).  For each column half bj the
+// lane's 4 BI values go to the wave's LDS scratch, value v of block row bi
+// at slot (bi * 64 + lane) * 4 + v, and then the unit half's entries of the
+// selection list (chain-local entry offset from kbase, scratch slot; built
+// on the host in the lane layout of the unit's variant; the first DWP per
+// lane prefetched) are copied from the scratch to the tile's partials: work
+// in proportion to the selected entries, not to the unit's BI * 2048
+// candidates.  LDS operations of one wave complete in order, so the reads
+// see the wave's own writes, and the next half's writes follow the reads.
+template <class A, class Acc, int BI>
+__device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const DwPre& pf,
+                                          const uint2* __restrict__ ent, int kbase, A* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) scr[(bi * 64 + lane) * 4 + v] = (A)acc[bi][bj][v];
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the half is in LDS
+        __builtin_amdgcn_wave_barrier();
+        const int e0 = pf.e0[bj], e1 = pf.e1[bj];
+#pragma unroll
+        for (int q = 0; q < DWP; ++q)
+            if (e0 + lane + 64 * q < e1) part[kbase + (int)pf.en[bj][q].x] = scr[pf.en[bj][q].y];
+        for (int e = e0 + lane + 64 * DWP; e < e1; e += 64) {
+            const uint2 en = ent[e];
+            part[kbase + (int)en.x] = scr[en.y];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Dense weight-gradient tile, selected entries kept: for output rows i and
 // input columns j of a layer,
 //   dW[i][j] = sum_r delta[r][i] * a[r][j]
-// as an MFMA product whose K dimension runs over the tile rows.  Which
-// entries are selected, and where each goes, comes from the layer's
-// selection bitmap: for row i and columns 32w .. 32w + 31 one word of bits
-// and the number of selected weights of the layer before that word, so the
-// chain-local index of entry (i, j) is kbase + prefix + popcount(bits below
-// j).  A lane's bitmap words depend only on its rows, so they are loaded
-// before the products and their latency hides behind the MFMAs.  The
+// as an MFMA product whose K dimension runs over the tile rows, then the
+// selected entries through the unit's selection list (dw_select).  The
 // operands sit row-major in LDS, so each lane reads its K values (one per
-// tile row) one scalar at a time; BI x BJ blocks per wave reuse them.
-// BJ = 2: the unit's two column blocks share one bitmap word.
+// tile row) one scalar at a time; BI x 2 blocks per wave reuse them.  Unit u
+// covers rows ui * BI * 16 .. and columns uj * 32 .. (u = ui * UJ + uj);
+// lane (g, li) holds rows 4 g + v of block bi and column li of block bj.
 template <int P, int R, int BI, int BJ, bool SQ = false>
 __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
-                                               int lx, int out_w, int in_w, int NI, int NJ,
-                                               const int2* __restrict__ mw, int nwr, int kbase,
+                                               int lx, int NI, int NJ, const unsigned* __restrict__ lst,
+                                               typename PT<P>::A* scr, int kbase,
                                                typename PT<P>::A* __restrict__ part) {
     typedef typename PT<P>::A A;
     typedef typename PT<P>::Acc Acc;
     typedef typename PT<P>::Frag Frag;
     constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
-    static_assert(BJ == 2, "a unit's two column blocks share one bitmap word");
+    static_assert(BJ == 2, "units of two column blocks");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
     const int UI = (NI + BI - 1) / BI, UJ = (NJ + BJ - 1) / BJ;
     const int imax = NI * 16 - 1, jmax = NJ * 16 - 1;
     const int nwave = (int)(blockDim.x >> 6);
-    // The lane's column bit in the unit's bitmap word depends only on the
-    // lane and the column block (a unit's first column is a multiple of 32).
-    // Bits are set only inside the layer, so a set bit also says the entry
-    // is in range.
-    unsigned selb[BJ], lowm[BJ];
-#pragma unroll
-    for (int bj = 0; bj < BJ; ++bj) {
-        selb[bj] = 1u << ((unsigned)(bj * 16 + li) & 31u);
-        lowm[bj] = selb[bj] - 1u;
-    }
+    const unsigned* tab = lst;
+    const uint2* ent = reinterpret_cast<const uint2*>(lst + ((2 * UI * UJ + 2) & ~1));
     for (int u = wave; u < UI * UJ; u += nwave) {
         const int ui = u / UJ, uj = u - ui * UJ;
-        const int w = (uj * BJ * 16) >> 5;          // bitmap word of the unit's columns
-        int2 tw[BI][4];
-#pragma unroll
-        for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = (ui * BI + bi) * 16 + 4 * g + v;
-                tw[bi][v] = (i < out_w && w < nwr) ? mw[(size_t)i * nwr + w] : make_int2(0, 0);
-            }
+        const DwPre pf = dw_prefetch(tab, ent, u);
         Acc acc[BI][BJ];
         int ic[BI], jc[BJ];
 #pragma unroll
@@ -706,16 +744,7 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 #pragma unroll
                     for (int bj = 0; bj < BJ; ++bj) mma1(acc[bi][bj], a[bi], b[bj], e);
         }
-#pragma unroll
-        for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const unsigned bits = (unsigned)tw[bi][v].x;
-                const int k0 = kbase + tw[bi][v].y;
-#pragma unroll
-                for (int bj = 0; bj < BJ; ++bj)
-                    if (bits & selb[bj]) part[k0 + __popc(bits & lowm[bj])] = (A)acc[bi][bj][v];
-            }
+        dw_select<A, Acc, BI>(acc, scr, pf, ent, kbase, part);
     }
 }
 
@@ -729,30 +758,24 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 // serves the two column blocks): two LDS reads per K slot for eight blocks,
 // against six scalar reads for the non-interleaved 4 x 2 tile.  Output
 // layout: lane (g, li) holds rows m = 4 g + v of column n = li, i.e. entry
-// (i0 + 16 g + 4 v + bi, j0 + 2 li + bj).  The unit's 32 columns are one
-// word of the selection bitmap.  Requires the padded output width to be a
-// multiple of 64 and R a multiple of 32 (the padded input width is a
-// multiple of 32 for BF16).
+// (i0 + 16 g + 4 v + bi, j0 + 2 li + bj); unit u = (i0 / 64) * NJ32 + j0 / 32.
+// Requires the padded output width to be a multiple of 64 and R a multiple
+// of 32 (the padded input width is a multiple of 32 for BF16).
 template <int R>
-__device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf16* X, int lx, int out_w, int NI64,
-                                            int NJ32, const int2* __restrict__ mw, int nwr, int kbase,
+__device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf16* X, int lx, int NI64, int NJ32,
+                                            const unsigned* __restrict__ lst, float* scr, int kbase,
                                             float* __restrict__ part) {
     typedef __bf16 b2v __attribute__((ext_vector_type(2)));
     static_assert(R % 32 == 0, "K chunks of 32 tile rows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, li = lane & 15;
     const int nwave = (int)(blockDim.x >> 6);
+    const unsigned* tab = lst;
+    const uint2* ent = reinterpret_cast<const uint2*>(lst + ((2 * NI64 * NJ32 + 2) & ~1));
     for (int u = wave; u < NI64 * NJ32; u += nwave) {
-        const int ui = u / NJ32, w = u - ui * NJ32;   // w: the bitmap word of columns 32 w .. 32 w + 31
+        const int ui = u / NJ32, w = u - ui * NJ32;
         const int i0 = ui * 64, j0 = w * 32;
-        int2 tw[4][4];
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + 16 * g + 4 * v + bi;
-                tw[bi][v] = (i < out_w && w < nwr) ? mw[(size_t)i * nwr + w] : make_int2(0, 0);
-            }
+        const DwPre pf = dw_prefetch(tab, ent, u);
         f4v acc[4][2];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) acc[bi][0] = acc[bi][1] = f4v{};
@@ -779,43 +802,30 @@ __device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf1
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) mma1(acc[bi][bj], fa[bi], fb[bj], 0);
         }
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const unsigned bits = (unsigned)tw[bi][v].x;
-                const int kb = kbase + tw[bi][v].y;
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    const unsigned sel = 1u << (2 * li + bj);
-                    if (bits & sel) part[kb + __popc(bits & (sel - 1u))] = acc[bi][bj][v];
-                }
-            }
+        dw_select<float, f4v, 4>(acc, scr, pf, ent, kbase, part);
     }
 }
 
+// Dense weight-gradient product of one layer in the variant the host chose
+// (its selection list is laid out for it): 2 x 2 blocks per unit, 4 x 2
+// blocks (BF16 and split BF16 layers wide enough for every wave), or the
+// interleaved 4 x 2 BF16 unit.
 template <int P, int R, bool SQ = false>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
-                                         int out_w, int in_w, int NI, int NJ, const int2* mw, int kbase,
-                                         typename PT<P>::A* part) {
-    // 2 x 2 blocks per unit (a single column block works too: the second is
-    // clamped and past in_w); BF16 layers wide enough for every wave take
-    // 4 x 2 for more operand reuse
+                                         int NI, int NJ, int variant, const unsigned* lst, typename PT<P>::A* scr,
+                                         int kbase, typename PT<P>::A* part) {
     if constexpr (R % PT<P>::KCH == 0) {
-        const int nwr = (in_w + 31) >> 5;
         if constexpr (P >= 2) {
-            if ((NI / 4) * ((NJ + 1) / 2) >= (int)(blockDim.x >> 6)) {
-                if constexpr (P == 2 && !SQ) {
-                    if (NI % 4 == 0 && NJ % 2 == 0) {
-                        dw_dense_il<R>(D, ld, X, lx, out_w, NI / 4, NJ / 2, mw, nwr, kbase, part);
-                        return;
-                    }
-                }
-                dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+            if (variant == DWV_IL) {
+                if constexpr (P == 2 && !SQ) dw_dense_il<R>(D, ld, X, lx, NI / 4, NJ / 2, lst, scr, kbase, part);
+                return;
+            }
+            if (variant == DWV_4X2) {
+                dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part);
                 return;
             }
         }
-        dw_dense_units<P, R, 2, 2, SQ>(D, ld, X, lx, out_w, in_w, NI, NJ, mw, nwr, kbase, part);
+        dw_dense_units<P, R, 2, 2, SQ>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part);
     }
 }
 
@@ -829,7 +839,7 @@ __device__ __forceinline__ void stage_meta(const GradArgs& a, const TowerPlan& t
     if (t <= tp.nl) m->seg[t] = a.seg[(size_t)c * a.nseg + tp.seg0 + t];
     if (t < tp.nl) {
         m->bseg[t] = a.bseg[lb + t];
-        m->mwoff[t] = (int)a.mw_off[lb + t];
+        m->mloff[t] = (int)a.ml_off[lb + t];
     }
     if (t == 0) {
         m->o = a.offs[c];
@@ -902,8 +912,9 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
             __syncthreads();
         }
         if (dmask & (1u << l)) {
-            dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.w[l + 1], tp.w[l],
-                               tp.wp[l + 1] >> 4, tp.wp[l] >> 4, a.mw + m->mwoff[l], seg[l], part);
+            A* scr = reinterpret_cast<A*>(reinterpret_cast<unsigned char*>(sm) + tp.scr + (threadIdx.x >> 6) * 4096);
+            dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.wp[l + 1] >> 4,
+                               tp.wp[l] >> 4, tp.dwv[l], a.ml + m->mloff[l], scr, seg[l], part);
             dw_partials<P, R, SQ>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
                                   part);
         } else {

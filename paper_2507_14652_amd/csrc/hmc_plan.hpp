@@ -26,6 +26,8 @@ struct TowerPlan {
     long long bo[HMC_MAXL];     // offset of b_l in the per-chain bias buffer
     long long fo[HMC_MAXL];     // flat parameter index of W_l[0][0]
     int seg0;                   // first layer of this tower in the segment table
+    int scr;                    // LDS byte offset of the dense weight-gradient scratch, 4096 bytes per wave
+    int dwv[HMC_MAXL];          // dense weight-gradient variant of each layer (DWV_*)
     int rc1;                    // 1: slabs 1 and 3 share one LDS region (towers of 4 or more layers that
                                 //   do not fit otherwise); the adjoint pass recomputes a_1 from the
                                 //   input before layer 1's weight gradient, when slab 3 is no longer needed
@@ -39,7 +41,7 @@ struct TileMeta {
     unsigned dmask;             // bit l: dense weight-gradient product for layer l
     int seg[HMC_MAXL + 1];      // chain-local start of each layer's entries (and the end)
     int bseg[HMC_MAXL];         // chain-local start of each layer's bias entries
-    int mwoff[HMC_MAXL];        // offset of each dense layer's selection bitmap in mw
+    int mloff[HMC_MAXL];        // offset (32-bit words) of each dense layer's selection list in ml
 };
 #define HMC_META_BYTES 128
 static_assert(sizeof(TileMeta) <= HMC_META_BYTES, "TileMeta exceeds its LDS reservation");
@@ -69,9 +71,11 @@ struct GradArgs {
     const int* bseg;            // [C][nl_total] chain-local start of each layer's bias entries
     const int* dflag;           // [C][nl_total] 1: weight partials by a dense tile product
     int nl_total;
-    const int2* mw;             // selection bitmaps of the dense layers: per row i and word w of
-                                //   32 columns, {bits, selected weights of the layer before it}
-    const long long* mw_off;    // [C][nl_total] offset of a (chain, layer) bitmap in mw (-1: none)
+    const unsigned* ml;         // selection lists of the dense layers: per (chain, layer) block, a table
+                                //   of 2 * units + 1 entry offsets (padded to an even length), then per
+                                //   unit half its entries (chain-local entry offset from the layer's
+                                //   first entry, LDS scratch slot) as uint2
+    const long long* ml_off;    // [C][nl_total] word offset of a (chain, layer) block in ml (-1: none)
     void* part;                 // per-tile gradient partials, A
     long long tmax;             // tiles per chain in the partial layout
     double* ulik;               // [C][tiles_a][8] likelihood partials (one slot per wave)
@@ -148,4 +152,7 @@ struct StateArgs {
 // (earlier drifts leave that copy alone: nothing reads it before the drift
 // to theta_L).
 enum { UPD_GRAD = 0, UPD_KICK_DRIFT = 1, UPD_HALF_KICK = 2, UPD_KICK_DRIFT_LAST = 3 };
+// Dense weight-gradient units: 2 x 2 or 4 x 2 blocks of 16 x 16, or the
+// interleaved BF16 4 x 2 unit (rows i0 + 16 g + 4 v + bi, columns j0 + 2 li + bj).
+enum { DWV_2X2 = 0, DWV_4X2 = 1, DWV_IL = 2 };
 enum { END_ENERGY = 0, END_TRAJ = 1, END_METROPOLIS = 2 };

@@ -74,13 +74,16 @@ def test_synced_trajectories_against_the_exact_leapfrog(label, make, prec):
           f"decisions differ {d_rate:.4f}; acceptance {a_gpu:.3f} vs {a_ref:.3f}")
     assert 0.2 < a_ref < 0.98                         # the decision test is not vacuous
     deep = "DeepONet" in label
-    # (p99 of the position error, fraction of differing decisions, acceptance difference); None: not bounded
+    # (p99 of the position error, fraction of differing decisions, acceptance
+    # difference): the 1% acceptance target where a precision meets it, and
+    # measured values with a margin as regression bounds where it does not
+    # (BF16 everywhere: 57% and 83% of the decisions differ; split BF16 on
+    # the stiff MLP posterior: 61%)
     bounds = {
         "fp64": (1e-12, 0.002, 0.002),
         "fp32": (1e-5, 0.01 if deep else 0.015, 0.01),
-        "bf16x3": (1e-4 if deep else 1e-5, 0.01 if deep else None, 0.01 if deep else None),
-        "bf16": (0.05, None, None),
+        "bf16x3": (1e-4, 0.01, 0.01) if deep else (1e-5, 0.75, 0.70),
+        "bf16": (0.05, 0.70, 0.65) if deep else (0.05, 0.95, 0.90),
     }[prec]
     assert np.quantile(eth, 0.99) <= bounds[0]
-    if bounds[1] is not None:
-        assert d_rate <= bounds[1] and abs(a_gpu - a_ref) <= bounds[2]
+    assert d_rate <= bounds[1] and abs(a_gpu - a_ref) <= bounds[2]
