@@ -1284,7 +1284,7 @@ namespace {
 // (entries past p zero).  For any vectors a_r,
 // sum_rows (f_row . a)^2 = a^T G a = sum_m (l_m . a)^2, so the l_m seed
 // the same sum of squared output derivatives in rank passes.
-std::vector<double> gram_factor(const std::vector<double>& F, long long rows, int p, int ld, int& rank) {
+static std::vector<double> gram_factor(const std::vector<double>& F, long long rows, int p, int ld, int& rank) {
     std::vector<double> G((size_t)p * p, 0.0);
     for (long long r = 0; r < rows; ++r) {
         const double* f = F.data() + (size_t)r * ld;
