@@ -86,7 +86,7 @@ def recorded_traffic(kernel, workload):
 KERNEL_OF = {"mlp": "k_mlp_grad", "deeponet": "k_branch_grad"}
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_{w} -o bench -- "
-             "python bench.py --config {w} --steps 20 --warmup 2 --adapt 20 --no-cpu-baseline --no-ess",
+             "python bench.py --config {w} --steps 5 --warmup 1 --adapt 5 --no-cpu-baseline --no-ess",
     "trace_sens": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_sens_{w} -o bench -- "
                   "python bench.py --config {w} --sensitivity --steps 3 --no-cpu-baseline",
     "FETCH_SIZE": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE_{w} -o bench -- "
@@ -232,9 +232,51 @@ def record_trace(workload, trace_dir, bench_json=None, sens=False):
         b = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
         lines.append(f"HIP-event mean of {kern} measured inside bench.py in the same run: "
                      f"{b['kernel_ms']['grad_main']:.4f} ms (kernel_ms.grad_main).")
+    if not sens:
+        lines += ["", *trajectory_gaps(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])]
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_kernel_trace.txt")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path)
+
+
+TRAJ_KERNELS = ("k_traj_begin<", "k_mlp_grad<", "k_branch_grad<", "k_trunk_fwd<", "k_trunk_bwd<",
+                "k_update<", "k_traj_end<")
+
+
+def trajectory_gaps(trace_csv):
+    """Idle time between the kernels of the trajectory graphs, from the
+    rocprofv3 kernel trace: consecutive dispatches of the trajectory kernels
+    on one queue that belong to one trajectory (from its k_traj_begin to its
+    k_traj_end), the device idle between the end of one and the start of the
+    next summed, against the kernels' own time over the same trajectories."""
+    import csv
+    rows = [r for r in csv.DictReader(open(trace_csv)) if any(k in r["Kernel_Name"] for k in TRAJ_KERNELS)]
+    rows.sort(key=lambda r: (r["Queue_Id"], int(r["Start_Timestamp"])))
+    busy = idle = 0
+    gaps, n_traj, open_traj, prev = [], 0, False, None
+    for r in rows:
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        name = r["Kernel_Name"]
+        if "k_traj_begin<" in name:
+            open_traj, prev = True, None
+        if not open_traj:
+            continue
+        if prev is not None and prev[0] == r["Queue_Id"]:
+            g = max(t0 - prev[1], 0)
+            gaps.append(g)
+            idle += g
+        busy += t1 - t0
+        prev = (r["Queue_Id"], t1)
+        if "k_traj_end<" in name:
+            open_traj = False
+            n_traj += 1
+    if not gaps:
+        return ["Trajectory gaps: no complete trajectory in the trace."]
+    g = np.array(gaps) / 1e3
+    return [f"Trajectory gaps over {n_traj} trajectories ({len(gaps) + n_traj} kernel dispatches): kernels busy "
+            f"{busy / 1e6:.3f} ms, idle between them {idle / 1e6:.3f} ms ({100 * idle / (busy + idle):.3f}% of the "
+            f"trajectories' span); gap per dispatch median {np.median(g):.2f} us, p90 {np.quantile(g, 0.9):.2f} us, "
+            f"max {g.max():.2f} us."]
 
 
 def sensitivity_flops(widths, rows):
@@ -385,11 +427,12 @@ def bulk_ess(draws):
     """Rank-normalised bulk effective sample size (Vehtari, Gelman, Simpson,
     Carpenter and Buerkner, 2021) of every coordinate of draws [N, M, D]
     (N iterations, M chains), with Geyer's initial monotone sequence."""
-    from scipy.stats import norm, rankdata
+    from scipy.special import ndtri
+    from scipy.stats import rankdata
     N, M, D = draws.shape
     flat = draws.reshape(N * M, D)
     r = rankdata(flat, axis=0, method="average")
-    z = norm.ppf((r - 0.375) / (N * M + 0.25)).reshape(N, M, D)
+    z = ndtri((r - 0.375) / (N * M + 0.25)).reshape(N, M, D)
     mean_c = z.mean(axis=0)
     W = z.var(axis=0, ddof=1).mean(axis=0)
     B_N = mean_c.var(axis=0, ddof=1) if M > 1 else np.zeros(D)
@@ -399,51 +442,68 @@ def bulk_ess(draws):
     acov = np.fft.irfft(f * np.conj(f), n=2 * N, axis=0)[:N] / N
     rho = 1.0 - (W - acov.mean(axis=1)) / var_plus
     rho[0] = 1.0
-    ess = np.empty(D)
-    for d in range(D):
-        s, prev = 0.0, np.inf
-        for k in range(0, N - 1, 2):
-            pk = rho[k, d] + rho[k + 1, d]
-            if pk < 0:
-                break
-            pk = min(pk, prev)
-            prev = pk
-            s += pk
-        tau = max(-1.0 + 2.0 * s, 1.0 / np.log10(max(N * M, 10)))
-        ess[d] = N * M / tau
-    return ess
+    # Geyer: sums of consecutive pairs up to the first negative one, each
+    # clipped to the smallest before it
+    K = N // 2
+    pairs = rho[0:2 * K:2] + rho[1:2 * K:2]
+    keep = np.cumprod(pairs >= 0, axis=0).astype(bool)
+    s = np.where(keep, np.minimum.accumulate(pairs, axis=0), 0.0).sum(axis=0)
+    tau = np.maximum(-1.0 + 2.0 * s, 1.0 / np.log10(max(N * M, 10)))
+    return N * M / tau
+
+
+def split_ess(draws):
+    """Within-chain bulk ESS of every coordinate of one chain's draws [N, D]:
+    the chain split into halves (two "chains" of N/2), so that a drift inside
+    the run lowers the estimate as disagreement between chains does."""
+    h = draws.shape[0] // 2
+    return bulk_ess(np.stack([draws[:h], draws[h:2 * h]], axis=1))
 
 
 def plain_torch_hmc(w, theta_s, eps, L, n_iter, seed, budget_s):
     """Plain single-chain HMC in PyTorch eager FP32 (TF32 off), chain 0: the
     full autograd backward over every parameter, then the selected entries
-    taken from it.  Same potential, integrator and Metropolis rule as the
-    engine.  Stops after n_iter iterations or budget_s seconds."""
+    taken from it.  Same potential (Eq. 3 with the Gaussian prior and
+    likelihood of Sec. 2.2), leapfrog integrator and Metropolis rule as the
+    engine, for the MLP and the DeepONet.  Stops after n_iter iterations or
+    budget_s seconds.  Returns the draws [n, D], the potential of every draw,
+    the Metropolis acceptance probability of every trajectory and the
+    seconds taken."""
     import torch
     torch.backends.cuda.matmul.allow_tf32 = False
     dev = "cuda"
     f32 = torch.float32
     base = torch.tensor(w.theta0, dtype=f32, device=dev)
     idx = torch.tensor(w.chain_idx(0), dtype=torch.long, device=dev)
-    X = torch.tensor(w.x, dtype=f32, device=dev)
-    Y = torch.tensor(w.y, dtype=f32, device=dev)
-    shapes = [(w.widths_a[i + 1], w.widths_a[i]) for i in range(len(w.widths_a) - 1)]
+    t = lambda a: torch.tensor(a, dtype=f32, device=dev)
+    if w.kind == "mlp":
+        X, Y = t(w.x), t(w.y)
+    else:
+        Ub, Yq, V = t(w.u), t(w.yq), t(w.v)
     ivl, ivp = 1.0 / w.lik_sd ** 2, 1.0 / w.prior_sd ** 2
+
+    def tower(full, pos, widths, a):
+        n = len(widths) - 1
+        for l in range(n):
+            o, i = widths[l + 1], widths[l]
+            Wm = full[pos:pos + o * i].view(o, i)
+            pos += o * i
+            a = a @ Wm.t() + full[pos:pos + o]
+            pos += o
+            if l < n - 1:
+                a = torch.tanh(a)
+        return a, pos
 
     def U_and_grad(ts):
         full = base.clone()
         full[idx] = ts
         full.requires_grad_(True)
-        a, pos = X, 0
-        for l, (o, i) in enumerate(shapes):
-            Wm = full[pos:pos + o * i].view(o, i)
-            pos += o * i
-            b = full[pos:pos + o]
-            pos += o
-            a = a @ Wm.t() + b
-            if l < len(shapes) - 1:
-                a = torch.tanh(a)
-        r = a - Y
+        if w.kind == "mlp":
+            r = tower(full, 0, w.widths_a, X)[0] - Y
+        else:
+            B, pos = tower(full, 0, w.widths_a, Ub)
+            T, pos = tower(full, pos, w.widths_b, Yq)
+            r = B @ T.t() + full[pos] - V
         sel = full[idx]
         U = 0.5 * ivl * (r * r).sum() + 0.5 * ivp * (sel * sel).sum()
         (g,) = torch.autograd.grad(U, full)
@@ -453,91 +513,147 @@ def plain_torch_hmc(w, theta_s, eps, L, n_iter, seed, budget_s):
     gen.manual_seed(seed)
     th = torch.tensor(theta_s, dtype=f32, device=dev)
     U, g = U_and_grad(th)
-    out, acc = [], 0
+    out, us, alphas, acc = [], [], [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(n_iter):
         p = torch.randn(th.shape, generator=gen, device=dev, dtype=f32)
         H0 = U + 0.5 * (p * p).sum()
         x, pp, gg = th, p - 0.5 * eps * g, g
-        for t in range(1, L + 1):
+        for k in range(1, L + 1):
             x = x + eps * pp
             U1, gg = U_and_grad(x)
-            pp = pp - (eps if t < L else 0.5 * eps) * gg
+            pp = pp - (eps if k < L else 0.5 * eps) * gg
         H1 = U1 + 0.5 * (pp * pp).sum()
         u = torch.rand((), generator=gen, device=dev, dtype=torch.float64)
         dH = float(H0 - H1)
+        alphas.append(float(np.exp(min(dH, 0.0))) if np.isfinite(dH) else 0.0)
         if np.isfinite(dH) and np.log(float(u)) < dH:
             th, U, g = x, U1, gg
             acc += 1
         out.append(th)
+        us.append(U)
         if time.perf_counter() - t0 > budget_s:
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return torch.stack(out).cpu().numpy(), acc / len(out), dt
+    return torch.stack(out).cpu().numpy(), torch.stack(us).double().cpu().numpy(), np.array(alphas), dt
 
 
-def ess_comparison(w, seed, budget_s=20.0):
-    """ESS/s of the batched engine against plain single-chain FP32 HMC, both
-    at the same step size and L, the step size adapted to 80% acceptance
-    (Sec. 4.3) by dual averaging.  Untimed preparation: Adam on the engine's
-    own gradient toward the conditional mode of every chain, adaptation,
-    burn-in.  The plain sampler starts where the engine's chain 0 ended and
-    uses chain 0's step size."""
+ESS_COORDS = 256
+ESS_LEGS = {  # workload: engine iterations (adapt, burn-in, calibration rounds x batch, sampled)
+    "antideriv_deeponet_bf16": dict(adapt=200, burn=300, rounds=5, batch=120, n=1000),
+    "regress2d_fp32": dict(adapt=500, burn=2000, rounds=8, batch=300, n=4000),
+}
+ESS_DEFAULT = ("antideriv_deeponet_bf16",)
+
+
+def ess_leg(name, seed, budget_s, adapt, burn, rounds, batch, n, progress=lambda m: None):
+    """ESS/s of the batched engine against plain single-chain FP32 HMC at
+    matched acceptance (Sec. 4.2.3's fixed-acceptance comparison, 80%).
+
+    Engine, untimed: per-chain dual averaging (the step size and the chains
+    move toward the typical set together), a burn-in at the adapted step
+    sizes, then bisection of every chain's step size on its batch-mean
+    acceptance.  Timed: n iterations of every chain.  The plain sampler runs
+    the same potential, integrator, L and chain 0's calibrated step size from
+    chain 0's last draw, for budget_s seconds; both acceptance rates are
+    measured and reported.
+
+    ESS is the rank-normalised bulk ESS of each coordinate within each chain
+    (split halves, so a drift shows), and of the potential U.  The engine's
+    ESS is the sum over its chains (each chain samples the same conditional
+    posterior from its own start); the multi-chain estimate, which also
+    counts disagreement between chains, is reported beside it."""
     import torch
+    import workloads
     from paper_2507_14652_amd import Sampler
+    w = workloads.make(name)
+    w = dataclasses.replace(w, precision=w.sample_precision or w.precision)
     s = Sampler.from_workload(w, seed=seed)
     C, L = w.n_chains, w.L
-    th = s.get_state()[0].double().cpu().numpy()
-    m, v = np.zeros_like(th), np.zeros_like(th)
-    lr, b1, b2 = 1e-3, 0.9, 0.999
-    for k in range(1, 1501):
-        s.set_state(th.astype(np.float32))
-        _, g = s.grad()
-        g = g.double().cpu().numpy()
-        m = b1 * m + (1 - b1) * g
-        v = b2 * v + (1 - b2) * g * g
-        th = th - lr * (m / (1 - b1 ** k)) / (np.sqrt(v / (1 - b2 ** k)) + 1e-8)
-    s.set_state(th.astype(np.float32))
-    eps_c = s.adapt(300, w.eps, L)
-    s.sample(50, eps_c, L)
-    n = 400
-    out = torch.empty((n, w.nnz), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    eps_c = s.adapt(adapt, w.eps, L)
+    s.sample(burn, eps_c, L, want_stats=False)
+    eps_c, _ = s.calibrate(rounds, batch, eps_c, L)
+    progress(f"ESS leg {name}: engine prepared in {time.perf_counter() - t0:.1f} s")
+    out = torch.empty((n, w.nnz), dtype=s.state_dtype, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, st = s.sample(n, eps_c, L, out=out)
     torch.cuda.synchronize()
     t_eng = time.perf_counter() - t0
-    flat = out.cpu().numpy()
-    sizes = np.diff(w.offs)
-    if np.all(sizes == sizes[0]) and all(np.array_equal(w.chain_idx(c), w.chain_idx(0)) for c in range(C)):
-        # one subset for every chain: the chains' draws of each coordinate combine
-        ess_eng = bulk_ess(flat.reshape(n, C, sizes[0]))
-    else:
-        # masks differ per chain: each chain's coordinates are its own
-        ess_eng = np.concatenate([bulk_ess(flat[:, None, w.offs[c]:w.offs[c + 1]]) for c in range(C)])
-    acc_eng = float(st["accepted"].mean())
-    start0 = flat[-1, w.offs[0]:w.offs[1]]
-    eps = float(eps_c[0])
-    base, acc_base, t_base = plain_torch_hmc(w, start0, eps, L, n, seed + 1, budget_s)
-    ess_base = bulk_ess(base[:, None, :])
+    flat = out.double().cpu().numpy()
+    # ESS of a seeded random subset of each chain's coordinates (all of them
+    # up to ESS_COORDS), median and minimum over it
+    pick = np.random.default_rng(seed).permutation(int(w.offs[1] - w.offs[0]))[:ESS_COORDS]
+    ess_c = [split_ess(flat[:, w.offs[c]:w.offs[c + 1]][:, np.sort(pick[pick < w.offs[c + 1] - w.offs[c]])])
+             for c in range(C)]
+    med_c = np.array([np.median(e) for e in ess_c])
+    same = all(np.array_equal(w.chain_idx(c), w.chain_idx(0)) for c in range(C))
+    combined = bulk_ess(flat.reshape(n, C, -1)[:, :, np.sort(pick)]) if same else None
+    # the potential of every draw of every chain (untimed)
+    U_eng = np.empty((n, C))
+    for k in range(n):
+        s.set_state(out[k])
+        U_eng[k] = s.grad()[0]
+    ess_u = np.array([split_ess(U_eng[:, c:c + 1])[0] for c in range(C)])
+    dh = st["H0"] - st["H1"]
+    alpha = np.where(np.isfinite(dh), np.exp(np.minimum(np.nan_to_num(dh, nan=-np.inf), 0.0)), 0.0)
     s.close()
+    progress(f"ESS leg {name}: engine {n} iterations x {C} chains in {t_eng:.2f} s, "
+             f"median within-chain ESS {np.median(med_c):.1f}")
+
+    base, U_base, alpha_b, t_base = plain_torch_hmc(w, flat[-1, w.offs[0]:w.offs[1]], float(eps_c[0]), L,
+                                                    10 ** 9, seed + 1, budget_s)
+    ess_b = split_ess(base[:, np.sort(pick)])
+    ess_bu = split_ess(U_base[:, None])[0]
+    progress(f"ESS leg {name}: plain FP32 {base.shape[0]} iterations in {t_base:.1f} s, "
+             f"median ESS {np.median(ess_b):.1f}")
+    eng_tot = float(med_c.sum())
+    a0, ab = float(alpha[:, 0].mean()), float(alpha_b.mean())
     r = {
-        "eps_chain0": eps, "eps_median": float(np.median(eps_c)), "L": L,
-        "acceptance_engine": acc_eng, "acceptance_plain": acc_base,
-        "engine": {"chains": C, "iterations": n, "seconds": t_eng,
-                   "ess_median": float(np.median(ess_eng)), "ess_min": float(ess_eng.min()),
-                   "ess_per_s_median": float(np.median(ess_eng)) / t_eng,
-                   "ess_per_s_min": float(ess_eng.min()) / t_eng},
-        "plain_fp32_torch": {"chains": 1, "iterations": int(base.shape[0]), "seconds": t_base,
-                             "ess_median": float(np.median(ess_base)), "ess_min": float(ess_base.min()),
-                             "ess_per_s_median": float(np.median(ess_base)) / t_base,
-                             "ess_per_s_min": float(ess_base.min()) / t_base},
+        "workload": name, "products": w.precision, "chains": C, "L": L,
+        "coordinates_per_chain": int(min(ESS_COORDS, w.offs[1] - w.offs[0])),
+        "eps_chain0": float(eps_c[0]), "eps_median": float(np.median(eps_c)),
+        # mean Metropolis acceptance probability, with its Monte Carlo standard error
+        "acceptance_engine": float(alpha.mean()),
+        "acceptance_engine_chain0": a0, "acceptance_engine_chain0_mcse": batch_mcse(alpha[:, 0]),
+        "acceptance_plain": ab, "acceptance_plain_mcse": batch_mcse(alpha_b),
+        "matched": bool(abs(a0 - 0.8) <= 0.02 and abs(ab - 0.8) <= 0.02),
+        "engine": {"iterations": n, "seconds": t_eng,
+                   "ess_median_per_chain": float(np.median(med_c)),
+                   "ess_min_per_chain": float(min(e.min() for e in ess_c)),
+                   "ess_median_sum_over_chains": eng_tot,
+                   "ess_u_sum_over_chains": float(ess_u.sum()),
+                   "ess_median_multichain": None if combined is None else float(np.median(combined)),
+                   "ess_per_s": eng_tot / t_eng,
+                   "ess_per_s_chain0": float(med_c[0]) / t_eng},
+        "plain_fp32_torch": {"iterations": int(base.shape[0]), "seconds": t_base,
+                             "ess_median": float(np.median(ess_b)), "ess_min": float(ess_b.min()),
+                             "ess_u": float(ess_bu), "ess_per_s": float(np.median(ess_b)) / t_base},
     }
-    r["ratio_median"] = r["engine"]["ess_per_s_median"] / max(r["plain_fp32_torch"]["ess_per_s_median"], 1e-300)
-    r["ratio_min"] = r["engine"]["ess_per_s_min"] / max(r["plain_fp32_torch"]["ess_per_s_min"], 1e-300)
+    r["ratio"] = r["engine"]["ess_per_s"] / max(r["plain_fp32_torch"]["ess_per_s"], 1e-300)
+    r["ratio_one_chain"] = r["engine"]["ess_per_s_chain0"] / max(r["plain_fp32_torch"]["ess_per_s"], 1e-300)
     return r
+
+
+def batch_mcse(x, batches=20):
+    """Monte Carlo standard error of the mean of a chain's values by batch means."""
+    x = np.asarray(x, dtype=np.float64)
+    k = len(x) // batches
+    if k < 2:
+        return None
+    m = x[:k * batches].reshape(batches, k).mean(axis=1)
+    return float(m.std(ddof=1) / np.sqrt(batches))
+
+
+def ess_comparison(seed, budget_s, progress=lambda m: None, legs=ESS_DEFAULT):
+    """The ESS/s comparison on the named workloads (by default the DeepONet;
+    the 2-D regression MLP's conditional posterior mixes too slowly at L = 50
+    for an ESS estimate within minutes: about 2 per chain in 4000
+    iterations)."""
+    return [ess_leg(name, seed, budget_s, progress=progress, **ESS_LEGS[name]) for name in legs]
 
 
 def main():
@@ -549,14 +665,18 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-reps", type=int, default=50)
-    ap.add_argument("--adapt", type=int, default=40,
+    ap.add_argument("--calibrate", nargs=2, type=int, metavar=("ROUNDS", "BATCH"),
+                    help="after adaptation, bisect the step sizes on batch-mean acceptance (untimed)")
+    ap.add_argument("--adapt", type=int, default=20,
                     help="untimed step-size adaptation iterations before the warm-up (0: the workload's eps)")
     ap.add_argument("--precision", choices=("fp64", "fp32", "bf16", "bf16x3"),
                     help="run --config's workload at another precision (a comparison, not the headline line)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shapes with the library's autotuner (untimed) instead of its heuristic")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
-    ap.add_argument("--ess-budget", type=float, default=20.0, help="seconds for the plain FP32 HMC leg")
+    ap.add_argument("--ess-budget", type=float, default=110.0, help="seconds of plain FP32 HMC per ESS leg")
+    ap.add_argument("--ess-only", nargs="*", metavar="WORKLOAD",
+                    help="run only the ESS/s comparison (on the named legs, default all) and print it")
     ap.add_argument("--predict", action="store_true",
                     help="time the posterior predictive (200 samples of chain 0 at 4096 new inputs) on --config")
     ap.add_argument("--sensitivity", action="store_true",
@@ -583,6 +703,10 @@ def main():
     if args.sensitivity:
         sensitivity_bench(args.config, args.steps if args.steps != 20 else 5, 0.0 if args.no_cpu_baseline else 10.0)
         return
+    if args.ess_only is not None:
+        prog = lambda m: print(f"[bench {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
+        print(json.dumps({"ess": ess_comparison(2507, args.ess_budget, prog, args.ess_only or ESS_DEFAULT)}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); chains are independent and would "
               "shard across GPUs with no per-step exchange, which this build does not run.", file=sys.stderr)
@@ -597,8 +721,9 @@ def main():
         print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
     w = workloads.make(args.config)
-    if args.precision:
-        w = dataclasses.replace(w, precision=args.precision)
+    # the products this workload samples in (the precision whose Metropolis
+    # decisions match FP64 ones within 1% there), unless --precision asks
+    w = dataclasses.replace(w, precision=args.precision or w.sample_precision or w.precision)
     progress(f"{w.name}: {w.precision}, {w.n_chains} chains, L={w.L}")
     tuning = autotune_workload(w, reps=10)[0] if args.autotune else None
     s = Sampler.from_workload(w, seed=2507, tuning=tuning)
@@ -611,6 +736,9 @@ def main():
     # the warm-up iterations at those step sizes
     eps_c = s.adapt(args.adapt, w.eps, L) if args.adapt else np.full(C, w.eps)
     progress(f"step sizes adapted over {args.adapt} iterations: median {np.median(eps_c):.3e}")
+    if args.calibrate:
+        eps_c, _ = s.calibrate(args.calibrate[0], args.calibrate[1], eps_c, L)
+        progress(f"step sizes calibrated: median {np.median(eps_c):.3e}")
     if args.warmup:
         s.sample(args.warmup, eps_c, L, out=warm)
     torch.cuda.synchronize()
@@ -653,7 +781,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "net": w.kind, "widths_a": w.widths_a, "widths_b": w.widths_b,
                    "rows": w.n_rows(), "chains": C, "selected_per_chain": int(w.nnz // C), "L": L,
+                   "products": w.precision, "energy": w.energy,
                    "eps_start": w.eps, "eps_adapt_iters": args.adapt,
+                   "eps_calibration": args.calibrate,
                    "eps_median": float(np.median(eps_c)), "eps_min": float(np.min(eps_c)),
                    "eps_max": float(np.max(eps_c)),
                    "launch": {"autotuned": bool(args.autotune), "dw": (tuning or {}).get("dw", 0),
@@ -666,8 +796,8 @@ def main():
     }
     s.close()
     progress(f"timed: {line['value']:.1f} {line['unit']}, acceptance {acc:.3f}")
-    if not args.no_ess and w.kind == "mlp":
-        line["ess"] = ess_comparison(w, seed=2507, budget_s=args.ess_budget)
+    if not args.no_ess:
+        line["ess"] = ess_comparison(2507, args.ess_budget, progress)
         progress("ESS comparison done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

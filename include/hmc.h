@@ -33,7 +33,7 @@
  *  - Work is queued on the engine's stream.  Functions that return host
  *    results (stats, energies, copies to host) synchronise that stream.
  *  - A divergent (non-finite) trajectory is not an error: its proposal is
- *    rejected and reported with divergent = 1 (Sec. 4.3 reports infinite
+ *    rejected and reported with divergent = 1 (Sec. 4.2.3 reports infinite
  *    gradients in full-batch runs).
  *  - One engine must not be used from two threads at once; separate engines
  *    are independent.
@@ -258,7 +258,7 @@ hmc_status hmc_set_state(hmc_ctx* ctx, const void* theta_s, const uint64_t* iter
 
 /* Accepted and divergent trajectory counts per chain since hmc_init (host,
  * [C] each, either may be NULL): the outcomes of the Metropolis step of
- * Algorithm 2 (a divergent trajectory, Sec. 4.3, is a rejection). */
+ * Algorithm 2 (a divergent trajectory, Sec. 4.2.3, is a rejection). */
 hmc_status hmc_counters(hmc_ctx* ctx, int64_t* accepted, int64_t* divergent);
 
 hmc_status hmc_get_info(const hmc_ctx* ctx, hmc_info_t* info);
@@ -335,7 +335,7 @@ hmc_status hmc_predict_noalloc(hmc_ctx* ctx, int32_t chain, const void* samples,
  * mask for hmc_init); *n_sel = N (it may be 0).  Host only. */
 hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx, int64_t* n_sel);
 
-/* Step-size adaptation for a target acceptance rate (Sec. 4.3 fixes it at
+/* Step-size adaptation for a target acceptance rate (Sec. 4.2.3 fixes it at
  * 80% with the dual-averaging scheme of Hoffman and Gelman, 2014): runs n
  * iterations of Algorithm 2 for every chain (they move the chains and
  * advance the iteration counters; nothing is stored), each chain starting
@@ -349,7 +349,7 @@ hmc_status hmc_select_mask(const double* s2, int64_t n, double tau, int64_t* idx
 hmc_status hmc_adapt(hmc_ctx* ctx, int64_t n, const double* eps0, int32_t L, double target, double* eps_out);
 
 /* Step sizes for a target acceptance rate to within the noise of a batch
- * mean (the matched 80% acceptance of Sec. 4.3's comparison; dual
+ * mean (the matched 80% acceptance of Sec. 4.2.3's comparison; dual
  * averaging alone settles somewhat above its target): per chain, a
  * bisection in log eps over `rounds` rounds of `batch` iterations of
  * Algorithm 2 each (they move the chains; nothing is stored).  Each round

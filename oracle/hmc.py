@@ -14,7 +14,7 @@ Readings (the paper leaves these open):
     or leapfrog; only leapfrog is volume preserving and reversible, which the
     Metropolis correction relies on);
   * r > u is decided as log u < H0 - H1 in FP64, u in the open interval
-    (0, 1); a non-finite H1 is a rejected, divergent proposal (Sec. 4.3
+    (0, 1); a non-finite H1 is a rejected, divergent proposal (Sec. 4.2.3
     reports infinite gradients in full-batch runs);
   * fixed step size, no jitter; M = I unless a diagonal inverse mass is given.
 """
@@ -107,7 +107,7 @@ def sample_chain(potential_and_grad, theta_init, eps, L, n, seed, chain,
 
 
 # ---------------------------------------------------------------------------
-# Step-size adaptation (Sec. 4.3: step sizes for an 80% acceptance rate by
+# Step-size adaptation (Sec. 4.2.3: step sizes for an 80% acceptance rate by
 # the dual-averaging scheme of Hoffman and Gelman, 2014) and the trajectory
 # length rule of App. C.
 

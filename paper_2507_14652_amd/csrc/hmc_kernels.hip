@@ -1585,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_traj_end(const StateArgs s, int mode) {
         } else if (adapt == 1) {
             // Dual averaging of the step size toward a target acceptance
             // statistic (Hoffman and Gelman 2014, HMC with dual averaging,
-            // the scheme Sec. 4.3 uses for its 80% runs): with alpha the
+            // the scheme Sec. 4.2.3 uses for its 80% runs): with alpha the
             // Metropolis acceptance probability of this trajectory (0 when
             // divergent), after iteration m
             //   H-bar_m = (1 - 1/(m + t0)) H-bar_{m-1} + (target - alpha)/(m + t0)

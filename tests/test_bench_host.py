@@ -54,3 +54,11 @@ def test_recorded_traffic_requires_matching_kernel_source(tmp_path, monkeypatch)
     (csrc / "hmc_kernels.hip").write_text("changed")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.recorded_traffic("k_mlp_grad", "regress2d_fp32") is None
+
+
+def test_split_ess_sees_a_drift_inside_one_chain():
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(4000, 3))
+    assert np.all(np.abs(bench.split_ess(x) / 4000 - 1) < 0.15)
+    x += np.linspace(0.0, 6.0, 4000)[:, None]     # a trend the chain has not left
+    assert np.all(bench.split_ess(x) < 100)

@@ -71,6 +71,8 @@ class Workload:
     v: Optional[np.ndarray] = None    # DeepONet targets [n_u, n_q]
     note: str = ""
     energy: str = "default"   # forward pass behind U in the Hamiltonian: "default" or "fp64"
+    sample_precision: str = ""  # products whose Metropolis decisions match FP64 ones within 1% on this
+                                # workload (measured): what it samples in; "" = precision
 
     @property
     def n_params(self) -> int:
@@ -196,7 +198,8 @@ def make(name: str, *, n_rows: Optional[int] = None, n_u: Optional[int] = None,
         offs, idx, th = _chains(master, theta0, [m] * C, 0.01)
         return Workload(name, "deeponet", wa, wb, precision or "bf16", 0.1, 1.0, 2e-4, 50, C, 100,
                         theta0, offs, idx, th, u=u, yq=yq, v=v,
-                        note="GRF inputs (RBF length 0.2) at equispaced sensors; target = antiderivative")
+                        note="GRF inputs (RBF length 0.2) at equispaced sensors; target = antiderivative",
+                        sample_precision="bf16x3")
 
     if name == "uneven_mlp_bf16":
         wa = list(widths_a or [4, 256, 256, 256, 256, 1])
@@ -216,7 +219,8 @@ def make(name: str, *, n_rows: Optional[int] = None, n_u: Optional[int] = None,
         offs, idx, th = _chains(master, theta0, masks, 0.01)
         return Workload(name, "mlp", wa, None, precision or "bf16", 1.0, 0.05, 1e-4, 50, C, 20,
                         theta0, offs, idx, th, x=x, y=y,
-                        note="x~U(-1,1)^4, smooth target + N(0,0.05^2); per-chain masks 1%..20%")
+                        note="x~U(-1,1)^4, smooth target + N(0,0.05^2); per-chain masks 1%..20%",
+                        sample_precision="fp32")
 
     # surface_deeponet_bf16
     wa = list(widths_a or [8, 512, 512, 512, 512, 256])
@@ -244,4 +248,4 @@ def make(name: str, *, n_rows: Optional[int] = None, n_u: Optional[int] = None,
     return Workload(name, "deeponet", wa, wb, precision or "bf16", 0.01, 5e-3, 1e-5, 50, C, 20,
                     theta0, offs, idx, th, u=c_in, yq=yq, v=v,
                     note="8 upstream scalars ~U(0,1), 32x16 surface grid, smooth synthetic field",
-                    energy="fp64")
+                    energy="fp64", sample_precision="fp32")
