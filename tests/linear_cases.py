@@ -6,8 +6,22 @@ Features come from a plain NumPy forward pass of the fixed layers.  Shared by
 the closed-form GPU tests; draws numbers only."""
 
 import numpy as np
+import pytest
 
 import workloads
+
+
+def engine(prec, desc):
+    """The engine for a case at a product precision; skips the test where
+    that precision's tiles of the case's widths do not fit in LDS."""
+    from paper_2507_14652_amd import Sampler
+    from paper_2507_14652_amd.binding import HMC_EUNSUPPORTED, HMCError
+    try:
+        return Sampler(precision=prec, **desc)
+    except HMCError as e:
+        if e.status == HMC_EUNSUPPORTED and "LDS" in str(e):
+            pytest.skip(f"{prec}: {e}")
+        raise
 
 
 def _tower(theta, widths, pos):
@@ -60,11 +74,13 @@ def _mlp_last_layer(name, n_chains, rng):
     return desc, Lam, m, const, sel.size, Phi, w.y[:, 0]
 
 
-def _deeponet_partial_branch(n_sel, n_chains, rng):
-    """The antiderivative DeepONet at its full size (1000 functions x 100
-    query points): n_sel random entries of the last branch layer plus b0
-    sampled, everything else (the trunk included) fixed."""
-    w = workloads.make("antideriv_deeponet_bf16", n_chains=1)
+def _deeponet_partial_branch(name, n_sel, n_chains, rng):
+    """A DeepONet workload at its full size (the antiderivative operator:
+    1000 functions x 100 query points; the surface operator: 2048 conditions
+    x 512 points): n_sel random entries of the last branch layer plus b0
+    sampled, everything else (the trunk included) fixed.  The engine
+    description carries the workload's energy setting."""
+    w = workloads.make(name, n_chains=1)
     theta0 = w.theta0.copy()
     br, pos = _tower(theta0, w.widths_a, 0)
     tr, pos = _tower(theta0, w.widths_b, pos)
@@ -98,12 +114,15 @@ def _deeponet_partial_branch(n_sel, n_chains, rng):
     starts = [m + Q @ (rng.standard_normal(m.size) / np.sqrt(ev)) for _ in range(n_chains)]
     desc = dict(kind="deeponet", widths_a=w.widths_a, widths_b=w.widths_b, theta0=theta0, prior_sd=w.prior_sd,
                 lik_sd=w.lik_sd, offs=np.arange(n_chains + 1) * sel.size, idx=np.tile(sel, n_chains),
-                theta_init=np.concatenate(starts), u=w.u, yq=w.yq, v=w.v)
+                theta_init=np.concatenate(starts), u=w.u, yq=w.yq, v=w.v, energy=w.energy)
     return desc, Lam, m, const, sel.size, Phi, (w.v - F_fixed).ravel()
 
 
 CASES = [
     ("regress2d_fp32 last layer", lambda rng: _mlp_last_layer("regress2d_fp32", 3, rng)),
     ("uneven_mlp_bf16 shape, last layer", lambda rng: _mlp_last_layer("uneven_mlp_bf16", 2, rng)),
-    ("antideriv DeepONet, 200 last-layer branch entries + b0", lambda rng: _deeponet_partial_branch(200, 2, rng)),
+    ("antideriv DeepONet, 200 last-layer branch entries + b0",
+     lambda rng: _deeponet_partial_branch("antideriv_deeponet_bf16", 200, 2, rng)),
+    ("surface DeepONet, 200 last-layer branch entries + b0",
+     lambda rng: _deeponet_partial_branch("surface_deeponet_bf16", 200, 2, rng)),
 ]

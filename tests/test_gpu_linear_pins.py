@@ -36,7 +36,7 @@ import torch
 pytestmark = pytest.mark.gpu
 
 
-from linear_cases import CASES, gaussian as _gaussian
+from linear_cases import CASES, engine, gaussian as _gaussian
 
 
 TOL = {"fp64": 1e-10, "fp32": 1e-5}
@@ -45,9 +45,8 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5}
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("label,make", CASES, ids=[c[0] for c in CASES])
 def test_gradient_and_potential_are_the_gaussian_closed_form(label, make, prec):
-    from paper_2507_14652_amd import Sampler
     desc, Lam, m, const, n, Phi, r0 = make(np.random.default_rng(11))
-    s = Sampler(precision=prec, **desc)
+    s = engine(prec, desc)
     U, g = s.grad()
     th = s.get_state()[0].double().cpu().numpy()
     g = g.double().cpu().numpy()
@@ -74,10 +73,9 @@ def test_trajectory_and_shadow_energy_closed_form(label, make, prec):
     """Positions after L steps against the leapfrog map with the closed-form
     gradient, and H1 - H0 against the shadow-energy identity, at a step size
     near the stability limit (eps sqrt(lam_max) = 1.2) so that dH is O(1)."""
-    from paper_2507_14652_amd import Sampler
     rng = np.random.default_rng(12)
     desc, Lam, m, const, n, _, _ = make(rng)
-    s = Sampler(precision=prec, **desc)
+    s = engine(prec, desc)
     C = len(desc["offs"]) - 1
     eps, L = 1.2 / math.sqrt(np.linalg.eigvalsh(Lam).max()), 25
     dt = np.float64 if prec == "fp64" else np.float32
