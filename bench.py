@@ -72,15 +72,18 @@ def algorithmic_flops(w, part=None):
     return total
 
 
-def recorded_traffic(kernel, workload):
+def recorded_traffic(kernel, workload, template=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy), or None
-    when the kernel source has changed since the counters were taken."""
+    when the kernel source has changed since the counters were taken or they
+    were taken on another instance (template: its name prefix)."""
     p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    return d["traffic_bytes_per_launch"] if d.get("kernel_source_sha256") == _kernel_sha() else None
+    if d.get("kernel_source_sha256") != _kernel_sha() or (template and d.get("template") != template):
+        return None
+    return d["traffic_bytes_per_launch"]
 
 
 KERNEL_OF = {"mlp": "k_mlp_grad", "deeponet": "k_branch_grad"}
@@ -100,6 +103,15 @@ PROFILE_CMDS = {
 COPY_BYTES = 64 * 2 ** 20 * 4
 
 
+PRECISION_INDEX = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+
+
+def main_kernel(w):
+    """The name prefix of the gradient kernel a workload's sampler runs, as
+    rocprofv3 prints it: its product precision, not the energy pass's."""
+    return f"{KERNEL_OF[w.kind]}<{PRECISION_INDEX[w.sample_precision or w.precision]}, "
+
+
 def _kernel_sha():
     src = os.path.join(ROOT, "paper_2507_14652_amd", "csrc", "hmc_kernels.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -107,12 +119,15 @@ def _kernel_sha():
 
 def _pmc_mean(csv_path, counter, name_part):
     """Mean per dispatch of `counter` over the kernels whose name contains
-    name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch count."""
+    name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch count.
+    Gradient kernels count only in their gradient form (template flag
+    false), not as the forward-only energy pass."""
     import csv
     vals = []
     with open(csv_path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+            k = r["Kernel_Name"]
+            if r["Counter_Name"] == counter and name_part in k and "true>" not in k:
                 vals.append(float(r["Counter_Value"]))
     if not vals:
         raise SystemExit(f"no {counter} rows for {name_part} in {csv_path}")
@@ -125,16 +140,17 @@ def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_di
     the counter reads for a plain device copy of known size."""
     import glob
     import workloads
-    kind = workloads.make(workload, n_chains=1).kind
-    kern = KERNEL_OF[kind]
+    w = workloads.make(workload, n_chains=1)
+    kern = KERNEL_OF[w.kind]
+    main = main_kernel(w)
     one = lambda d: glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
-    fk, nd = _pmc_mean(one(fetch_dir), "FETCH_SIZE", kern + "<")
-    wk, _ = _pmc_mean(one(write_dir), "WRITE_SIZE", kern + "<")
+    fk, nd = _pmc_mean(one(fetch_dir), "FETCH_SIZE", main)
+    wk, _ = _pmc_mean(one(write_dir), "WRITE_SIZE", main)
     cf, _ = _pmc_mean(one(copy_fetch_dir), "FETCH_SIZE", "copy")
     cw, _ = _pmc_mean(one(copy_write_dir), "WRITE_SIZE", "copy")
     ff, wf = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
     out = {
-        "kernel": kern, "workload": workload, "kernel_source_sha256": _kernel_sha(),
+        "kernel": kern, "template": main, "workload": workload, "kernel_source_sha256": _kernel_sha(),
         "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": nd,
         "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
                              "fetch_factor": ff, "write_factor": wf},
@@ -171,8 +187,9 @@ def record_mfma(workload, pmc_dir):
     rows = list(csv.DictReader(open(glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0])))
     names = ["k_mlp_grad<", "k_trunk_fwd<", "k_branch_grad<", "k_trunk_bwd<", "k_update<"]
     parts = {"k_mlp_grad<": None, "k_branch_grad<": "branch", "k_trunk_fwd<": None, "k_trunk_bwd<": None}
+    main = main_kernel(w)
     lines = [f"MFMA counters per dispatch: masked full-batch HMC, workload {workload} "
-             f"({w.precision.upper()}, {w.n_chains} chains, L={w.L})",
+             f"({(w.sample_precision or w.precision).upper()} products, {w.n_chains} chains, L={w.L})",
              f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
              "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
              "  " + PROFILE_CMDS["mfma"].format(w=workload), "",
@@ -180,22 +197,25 @@ def record_mfma(workload, pmc_dir):
              "executed = MOPS * 512 flops (padding to the MFMA tiles included)",
              f"{'kernel':<42}{'dispatches':>11}{'busy %':>9}{'executed GFLOP':>16}{'algorithmic GFLOP':>19}"]
     for n in names:
-        sel = [r for r in rows if n in r["Kernel_Name"]]
-        if not sel:
-            continue
-        kname = sel[0]["Kernel_Name"].replace("void (anonymous namespace)::", "")
-        per = {}
-        for r in sel:
-            per.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
-        full = [d for d in per.values() if all(c in d for c in MFMA_COUNTERS)]
-        mean = {c: sum(d[c] for d in full) / len(full) for c in MFMA_COUNTERS}
-        busy = 100.0 * mean["SQ_VALU_MFMA_BUSY_CYCLES"] / max(mean["GRBM_GUI_ACTIVE"] / N_XCD * N_SIMD, 1.0)
-        ex = 512.0 * (mean["SQ_INSTS_VALU_MFMA_MOPS_F32"] + mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] +
-                      mean["SQ_INSTS_VALU_MFMA_MOPS_F64"]) / 1e9
-        alg = ""
-        if n == "k_mlp_grad<" or n == "k_branch_grad<":
-            alg = f"{algorithmic_flops(w, parts[n]) / 1e9:.3f}"
-        lines.append(f"{kname[:41]:<42}{len(full):>11}{busy:>9.2f}{ex:>16.3f}{alg:>19}")
+        # one row per template instance (the gradient form and, where the
+        # energies take another precision, the forward-only energy pass)
+        for kname in sorted({r["Kernel_Name"] for r in rows if n in r["Kernel_Name"]}):
+            sel = [r for r in rows if r["Kernel_Name"] == kname]
+            per = {}
+            for r in sel:
+                per.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = float(r["Counter_Value"])
+            full = [d for d in per.values() if all(c in d for c in MFMA_COUNTERS)]
+            if not full:
+                continue
+            mean = {c: sum(d[c] for d in full) / len(full) for c in MFMA_COUNTERS}
+            busy = 100.0 * mean["SQ_VALU_MFMA_BUSY_CYCLES"] / max(mean["GRBM_GUI_ACTIVE"] / N_XCD * N_SIMD, 1.0)
+            ex = 512.0 * (mean["SQ_INSTS_VALU_MFMA_MOPS_F32"] + mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] +
+                          mean["SQ_INSTS_VALU_MFMA_MOPS_F64"]) / 1e9
+            short = kname.replace("void (anonymous namespace)::", "")
+            alg = ""
+            if n in ("k_mlp_grad<", "k_branch_grad<") and main in kname and "true>" not in kname:
+                alg = f"{algorithmic_flops(w, parts[n]) / 1e9:.3f}"
+            lines.append(f"{short[:41]:<42}{len(full):>11}{busy:>9.2f}{ex:>16.3f}{alg:>19}")
     path = os.path.join(ROOT, "profiles", f"{KERNEL_OF[w.kind]}_{workload}_mfma.txt")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path)
@@ -220,7 +240,8 @@ def record_trace(workload, trace_dir, bench_json=None, sens=False):
     else:
         head = [f"Kernel-trace summary: masked full-batch HMC, workload {workload}",
                 f"({net} tanh, {w.n_rows()} rows, {w.n_chains} chains, {w.nnz // w.n_chains} of {w.n_params} "
-                f"parameters sampled per chain on average, {w.precision.upper()}, L={w.L})"]
+                f"parameters sampled per chain on average, {(w.sample_precision or w.precision).upper()} "
+                f"products, L={w.L})"]
     lines = head + [f"Device: one MI355X (gfx950).  Kernel source sha256 (hmc_kernels.hip): {_kernel_sha()}",
              "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
              "  " + PROFILE_CMDS["trace_sens" if sens else "trace"].format(w=workload), "",
@@ -674,7 +695,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shapes with the library's autotuner (untimed) instead of its heuristic")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
-    ap.add_argument("--ess-budget", type=float, default=110.0, help="seconds of plain FP32 HMC per ESS leg")
+    ap.add_argument("--ess-budget", type=float, default=130.0, help="seconds of plain FP32 HMC per ESS leg")
     ap.add_argument("--ess-only", nargs="*", metavar="WORKLOAD",
                     help="run only the ESS/s comparison (on the named legs, default all) and print it")
     ap.add_argument("--predict", action="store_true",
@@ -755,7 +776,7 @@ def main():
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAK[DTYPE[w.precision]]
     kname = KERNEL_OF[w.kind]
-    traffic = recorded_traffic(kname, w.name)
+    traffic = recorded_traffic(kname, w.name, f"{kname}<{PRECISION_INDEX[w.precision]}, ")
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "kernel": kname, "kernel_ms": dom_ms, "flops_per_launch": flops,
             "hbm_gbps": traffic / (dom_ms * 1e-3) / 1e9 if traffic else None}
