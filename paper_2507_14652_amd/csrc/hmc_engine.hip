@@ -276,7 +276,9 @@ int pick_threads(size_t /*lds*/, int forced) {
 
 // Slab sharing (recompute) applies to towers with at least four linear
 // layers, where slab 3 holds a hidden activation.
-bool can_alias(const std::vector<int>& w) { return w.size() >= 5; }
+// Slabs 1 and 3 may share LDS in towers of four or more layers, at tile
+// heights of at most 32 rows (the 64-row kernels carry no recompute code).
+bool can_alias(const std::vector<int>& w, int r) { return w.size() >= 5 && r <= 32; }
 
 // LDS row stride (elements) of slab l.
 int slab_ld(const std::vector<int>& w, int prec, size_t l) { return roundup(w[l], pad_of(prec)) + lpad_of(prec); }
@@ -353,7 +355,7 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row, size_t 
 // is enough: the DeepONet trunk adjoint runs 50 -> 46 us at 32 rows instead
 // of 16).  A tower of four or more layers shares slabs 1 and 3 (alias,
 // recomputing a_1 in the adjoint pass: one tile product of the narrow input
-// layer) where that makes a taller tile fit.  A tuning value (16, 32 or 64;
+// layer) where that makes a taller tile of at most 32 rows fit.  A tuning value (16, 32 or 64;
 // 0 when it does not fit) or else HMC_ROWS_A / HMC_ROWS_B overrides the
 // height.  fixed: bytes beside the slabs (staged biases, alignment);
 // scr_bytes: the dense weight-gradient scratch, needed at tile heights that
@@ -366,12 +368,12 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
         return tower_lds(w, prec, r, al) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed + scr <= g_lds_cap;
     };
     const char* rc = std::getenv("HMC_RECOMPUTE");   // "1": share wherever possible (tests)
-    const bool force_alias = can_alias(w) && rc && !std::strcmp(rc, "1");
+    const bool force_alias = rc && !std::strcmp(rc, "1");
     // the sharing choice for one candidate height; false: it does not fit
     auto choose = [&](int r, bool& al) {
-        if (force_alias) { al = true; return fits_as(r, true); }
+        if (force_alias && can_alias(w, r)) { al = true; return fits_as(r, true); }
         if (fits_as(r, false)) { al = false; return true; }
-        if (can_alias(w) && fits_as(r, true)) { al = true; return true; }
+        if (can_alias(w, r) && fits_as(r, true)) { al = true; return true; }
         return false;
     };
     if (forced) return choose(forced, alias) ? forced : 0;

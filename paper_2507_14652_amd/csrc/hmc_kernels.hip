@@ -630,15 +630,20 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
 
 // Selection-list entries of one dense weight-gradient unit, loaded before
 // its product so that their latency overlaps the MFMAs: the unit halves'
-// entry ranges and each lane's first DWP entries of each half.
-constexpr int DWP = 4;
+// entry ranges and each lane's first D entries of each half.  Four for the
+// BF16 types; one for FP32 and FP64, whose dense path is taken only on
+// request and whose registers the FP32 kernels need for their occupancy.
+template <int P> constexpr int DWP = P >= 2 ? 4 : 1;
+template <int D>
 struct DwPre {
     int e0[2], e1[2];
-    uint2 en[2][DWP];
+    uint2 en[2][D];
 };
-__device__ __forceinline__ DwPre dw_prefetch(const unsigned* __restrict__ tab, const uint2* __restrict__ ent, int u) {
+template <int DWP>
+__device__ __forceinline__ DwPre<DWP> dw_prefetch(const unsigned* __restrict__ tab, const uint2* __restrict__ ent,
+                                                  int u) {
     const int lane = threadIdx.x & 63;
-    DwPre p;
+    DwPre<DWP> p;
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
         p.e0[bj] = (int)tab[2 * u + bj];
@@ -662,8 +667,8 @@ __device__ __forceinline__ DwPre dw_prefetch(const unsigned* __restrict__ tab, c
 // in proportion to the selected entries, not to the unit's BI * 2048
 // candidates.  LDS operations of one wave complete in order, so the reads
 // see the wave's own writes, and the next half's writes follow the reads.
-template <class A, class Acc, int BI>
-__device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const DwPre& pf,
+template <class A, class Acc, int BI, int DWP>
+__device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const DwPre<DWP>& pf,
                                           const uint2* __restrict__ ent, int kbase, A* __restrict__ part) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -715,7 +720,7 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
     const uint2* ent = reinterpret_cast<const uint2*>(lst + ((2 * UI * UJ + 2) & ~1));
     for (int u = wave; u < UI * UJ; u += nwave) {
         const int ui = u / UJ, uj = u - ui * UJ;
-        const DwPre pf = dw_prefetch(tab, ent, u);
+        const auto pf = dw_prefetch<DWP<P>>(tab, ent, u);
         Acc acc[BI][BJ];
         int ic[BI], jc[BJ];
 #pragma unroll
@@ -775,7 +780,7 @@ __device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf1
     for (int u = wave; u < NI64 * NJ32; u += nwave) {
         const int ui = u / NJ32, w = u - ui * NJ32;
         const int i0 = ui * 64, j0 = w * 32;
-        const DwPre pf = dw_prefetch(tab, ent, u);
+        const auto pf = dw_prefetch<DWP<2>>(tab, ent, u);
         f4v acc[4][2];
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) acc[bi][0] = acc[bi][1] = f4v{};
@@ -904,12 +909,16 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     const int* bseg = m->bseg;
     const unsigned dmask = m->dmask;
     for (int l = tp.nl - 1; l >= lowest; --l) {
-        if (l == 1 && tp.rc1) {
-            // the barrier that ended layer 2's adjoint product has retired
-            // every read of slab 3 (delta_3)
-            EpiTanh<P> e{B + tp.bo[0], sm + tp.lo[1], tp.ls[1]};
-            gemm<P, R>(W + tp.wo[0], tp.wp[0], tp.wp[0], tp.wp[1], sm + tp.lo[0], tp.ls[0], e);
-            __syncthreads();
+        // (slab sharing is planned for tiles of at most 32 rows only, so the
+        // 64-row instances carry no recompute code and its registers)
+        if constexpr (R <= 32) {
+            if (l == 1 && tp.rc1) {
+                // the barrier that ended layer 2's adjoint product has
+                // retired every read of slab 3 (delta_3)
+                EpiTanh<P> e{B + tp.bo[0], sm + tp.lo[1], tp.ls[1]};
+                gemm<P, R>(W + tp.wo[0], tp.wp[0], tp.wp[0], tp.wp[1], sm + tp.lo[0], tp.ls[0], e);
+                __syncthreads();
+            }
         }
         if (dmask & (1u << l)) {
             A* scr = reinterpret_cast<A*>(reinterpret_cast<unsigned char*>(sm) + tp.scr + (threadIdx.x >> 6) * 4096);
@@ -982,12 +991,19 @@ __device__ __forceinline__ double head_fp64(const GradArgs& a, const TowerPlan& 
     return sq;
 }
 
+// Waves per SIMD the register allocation must leave room for: four (two
+// 512-thread workgroups per compute unit, at most 128 VGPRs) for the FP32
+// MLP kernels of 64-row tiles, whose LDS footprint on narrow layers admits
+// a second workgroup; otherwise no constraint beyond one workgroup.
+template <int P, int R> constexpr int MLP_WAVES = (P == 1 && R == 64) ? 4 : 1;
+
 // ---------------------------------------------------------------------------
 // MLP: forward, head and adjoint of one (chain, row tile).
 // FWD = true: forward pass and likelihood partials only (the energy pass),
 // with activation slabs that may alias (ping-pong plans).
 template <int P, int R, bool FWD>
-__global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
+__global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVES<P, R>))) void k_mlp_grad(
+    const GradArgs a) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
@@ -1047,7 +1063,8 @@ __global__ __launch_bounds__(HMC_NT) void k_mlp_grad(const GradArgs a) {
 // function j.  tower 0: the MLP or branch tower (a.ta, a.xa), 1: the trunk
 // (a.tb, a.xb).  seed: product type, [wp_out], device.
 template <int P, int R>
-__global__ __launch_bounds__(HMC_NT) void k_tower_sens(const GradArgs a, int tower, const void* seed) {
+__global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVES<P, R>))) void k_tower_sens(
+    const GradArgs a, int tower, const void* seed) {
     typedef typename PT<P>::T T; typedef typename PT<P>::A A;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
