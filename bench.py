@@ -117,17 +117,26 @@ def _kernel_sha():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
+def energy_pass(kernel_name):
+    """Whether a gradient-kernel instance, as rocprofv3 names it, is the
+    forward-only energy pass (its third template argument, FWD, true)."""
+    if "<" not in kernel_name:
+        return False
+    args = kernel_name[kernel_name.index("<") + 1:].split(">")[0].split(",")
+    return len(args) >= 3 and args[2].strip() == "true"
+
+
 def _pmc_mean(csv_path, counter, name_part):
     """Mean per dispatch of `counter` over the kernels whose name contains
     name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch count.
-    Gradient kernels count only in their gradient form (template flag
-    false), not as the forward-only energy pass."""
+    Gradient kernels count only in their gradient form, not as the
+    forward-only energy pass."""
     import csv
     vals = []
     with open(csv_path) as f:
         for r in csv.DictReader(f):
             k = r["Kernel_Name"]
-            if r["Counter_Name"] == counter and name_part in k and "true>" not in k:
+            if r["Counter_Name"] == counter and name_part in k and not energy_pass(k):
                 vals.append(float(r["Counter_Value"]))
     if not vals:
         raise SystemExit(f"no {counter} rows for {name_part} in {csv_path}")
@@ -213,7 +222,7 @@ def record_mfma(workload, pmc_dir):
                           mean["SQ_INSTS_VALU_MFMA_MOPS_F64"]) / 1e9
             short = kname.replace("void (anonymous namespace)::", "")
             alg = ""
-            if n in ("k_mlp_grad<", "k_branch_grad<") and main in kname and "true>" not in kname:
+            if n in ("k_mlp_grad<", "k_branch_grad<") and main in kname and not energy_pass(kname):
                 alg = f"{algorithmic_flops(w, parts[n]) / 1e9:.3f}"
             lines.append(f"{short[:41]:<42}{len(full):>11}{busy:>9.2f}{ex:>16.3f}{alg:>19}")
     path = os.path.join(ROOT, "profiles", f"{KERNEL_OF[w.kind]}_{workload}_mfma.txt")

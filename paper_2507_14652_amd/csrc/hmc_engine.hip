@@ -132,6 +132,8 @@ struct hmc_ctx {
     int Ra = 0, Rb = 0, tiles_a = 0, tiles_b = 0;
     bool alias_a = false, alias_b = false;   // slabs 1 and 3 shared (a_1 recomputed in the adjoint pass)
     int grid_a = 0, grid_b = 0;
+    int tpg = 1;                  // MLP gradient kernel: row tiles per workgroup (tile_group)
+    int groups_a = 0, grid_mlp = 0;   // ... its tile groups per chain and its grid
     size_t lds_a = 0, lds_b = 0;
     int nt_a = 256, nt_b = 256, nt_a32 = 256, nt_b32 = 256;   // threads per workgroup
     bool force_dense = false;     // sensitivity engines: dense dW (squared terms) on every layer
@@ -392,6 +394,28 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
     return best;
 }
 
+// Row tiles per workgroup of the MLP gradient kernel: it sums the weight-
+// gradient terms of that many consecutive tiles of one chain into one
+// partial slot (read-modify-writes by the thread that owns each entry),
+// which divides the partials k_update reads by as much.  Groups of up to
+// eight while the grid keeps at least 16 workgroups per compute unit, for
+// FP32 products at 32-row tiles only, where the read-modify-writes cost
+// the gradient kernel nothing measurable (256-chain MLP: 79.7 against
+// 79.7 ms, k_update 1.91 -> 0.25 ms); at 16-row tiles they cost it 9%
+// (71.6 -> 78.3 ms, two resident workgroups per compute unit), and the
+// loop's registers cost a third of the BF16 kernel.
+// HMC_TILE_GROUP (1, 2, 4 or 8) overrides the size where groups apply.
+int tile_group(int prec, int R, int chains, int tiles) {
+    if (prec != HMC_FP32 || R != 32) return 1;
+    if (const char* s = std::getenv("HMC_TILE_GROUP")) {
+        const int g = std::atoi(s);
+        if (g == 1 || g == 2 || g == 4 || g == 8) return g;
+    }
+    int g = 1;
+    while (g < 8 && (long long)chains * ((tiles + 2 * g - 1) / (2 * g)) >= 16 * 256) g *= 2;
+    return g;
+}
+
 // Whether a tower may take the dense weight-gradient product on some layer
 // (so that its kernels need the per-wave scratch): BF16 and split-BF16
 // layers at least 64 wide on both sides, or any layer when dense is forced.
@@ -418,7 +442,7 @@ int dw_variant(int prec, int NI, int NJ, int nwave, bool sq) {
 hmc_status launch_grad(hmc_ctx* x, hipStream_t s) {
     const int P = x->prec;
     if (x->kind == HMC_MLP) {
-        HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, s));
+        HMC_HIP(x, hmc_launch_mlp_grad(P, x->Ra, x->nt_a, x->ga, x->grid_mlp, x->lds_a, s));
     } else {
         HMC_HIP(x, hmc_launch_trunk_fwd(P, x->Rb, x->nt_b, x->ga, x->grid_b, x->lds_b, s));
         HMC_HIP(x, hmc_launch_branch_grad(P, x->Ra, x->nt_a, x->ga, x->grid_a, x->lds_a, s));
@@ -554,6 +578,9 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
         return x->fail(HMC_EUNSUPPORTED, "grid too large");
     x->grid_a = roundup(x->C * x->tiles_a, 8);
     x->grid_b = roundup(x->C * x->tiles_b, 8);
+    x->tpg = x->force_dense || x->kind != HMC_MLP ? 1 : tile_group(prec, x->Ra, x->C, x->tiles_a);
+    x->groups_a = (x->tiles_a + x->tpg - 1) / x->tpg;
+    x->grid_mlp = roundup(x->C * x->groups_a, 8);
 
     GradArgs& g = x->ga;
     fill_plan(g.ta, x->A.w, prec, x->Ra, x->alias_a);
@@ -912,7 +939,8 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.ecode = code_d;
     g.seg = seg_d;
     g.nseg = nseg;
-    g.tmax = std::max(x->tiles_a, x->tiles_b);
+    g.tpg = x->tpg;
+    g.tmax = std::max(x->groups_a, x->tiles_b);
     g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
     g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * x->tiles_a);
     if (!g.part || !g.ulik) return x->fail(HMC_ENOMEM, "device allocation of the gradient partials failed");
@@ -1026,7 +1054,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     s.nseg = nseg;
     s.seg_trunk_lo = la;
     s.seg_trunk_hi = la + lb;
-    s.tiles_a = x->tiles_a;   // partials per chain and tower
+    s.tiles_a = x->groups_a;  // partials per chain and tower
     s.tiles_b = x->tiles_b;
     s.tmax = g.tmax;
     x->upd_sub = update_sub(x);

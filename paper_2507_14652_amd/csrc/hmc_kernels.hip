@@ -578,11 +578,12 @@ __device__ __forceinline__ void frag_put(typename PT<P>::Frag& f, int e, const t
     }
 }
 
-template <int P, int R, bool SQ = false>
+template <int P, int R, bool SQ = false, bool RMW = false>
 __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0, int k1,
                                             const typename PT<P>::T* D, int ld,
                                             const typename PT<P>::T* X, int lx,
-                                            typename PT<P>::A* __restrict__ part) {
+                                            typename PT<P>::A* __restrict__ part, bool accum_) {
+    const bool accum = RMW && accum_;   // RMW false: the accumulate paths compile out
     typedef typename PT<P>::A A;
     const int n = k1 - k0;
     if (n <= 0) return;
@@ -597,7 +598,10 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
             const int cd = cn;
             if (k + nthr < k1) cn = code[k + nthr];
             const int i = cd >> 16, j = cd & 0xFFFF;
+            // the running sum of the workgroup's earlier tiles (this thread
+            // wrote it), loaded before the sum so that its latency overlaps it
             A s = (A)0;
+            if constexpr (RMW) s = accum ? part[k] : (A)0;
             if (j == 0xFFFF) {
 #pragma unroll 8
                 for (int r = 0; r < R; ++r) s += sq_if<SQ>(ld1<P>(D + r * ld, i));
@@ -625,7 +629,10 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
         }
     }
     for (int o = 1; o < lpe; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (e < n && sub == 0) part[k0 + e] = s;
+    if (e < n && sub == 0) {
+        if constexpr (RMW) part[k0 + e] = accum ? part[k0 + e] + s : s;
+        else part[k0 + e] = s;
+    }
 }
 
 // Selection-list entries of one dense weight-gradient unit, loaded before
@@ -667,9 +674,11 @@ __device__ __forceinline__ DwPre<DWP> dw_prefetch(const unsigned* __restrict__ t
 // in proportion to the selected entries, not to the unit's BI * 2048
 // candidates.  LDS operations of one wave complete in order, so the reads
 // see the wave's own writes, and the next half's writes follow the reads.
-template <class A, class Acc, int BI, int DWP>
+template <class A, class Acc, int BI, int DWP, bool RMW = false>
 __device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const DwPre<DWP>& pf,
-                                          const uint2* __restrict__ ent, int kbase, A* __restrict__ part) {
+                                          const uint2* __restrict__ ent, int kbase, A* __restrict__ part,
+                                          bool accum_) {
+    const bool accum = RMW && accum_;   // RMW false: the accumulate paths compile out
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
@@ -682,10 +691,22 @@ __device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const
         const int e0 = pf.e0[bj], e1 = pf.e1[bj];
 #pragma unroll
         for (int q = 0; q < DWP; ++q)
-            if (e0 + lane + 64 * q < e1) part[kbase + (int)pf.en[bj][q].x] = scr[pf.en[bj][q].y];
+            if (e0 + lane + 64 * q < e1) {
+                if constexpr (RMW) {
+                    A* dst = part + kbase + (int)pf.en[bj][q].x;
+                    *dst = accum ? *dst + scr[pf.en[bj][q].y] : scr[pf.en[bj][q].y];
+                } else {
+                    part[kbase + (int)pf.en[bj][q].x] = scr[pf.en[bj][q].y];
+                }
+            }
         for (int e = e0 + lane + 64 * DWP; e < e1; e += 64) {
             const uint2 en = ent[e];
-            part[kbase + (int)en.x] = scr[en.y];
+            if constexpr (RMW) {
+                A* dst = part + kbase + (int)en.x;
+                *dst = accum ? *dst + scr[en.y] : scr[en.y];
+            } else {
+                part[kbase + (int)en.x] = scr[en.y];
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -700,11 +721,11 @@ __device__ __forceinline__ void dw_select(const Acc (&acc)[BI][2], A* scr, const
 // tile row) one scalar at a time; BI x 2 blocks per wave reuse them.  Unit u
 // covers rows ui * BI * 16 .. and columns uj * 32 .. (u = ui * UJ + uj);
 // lane (g, li) holds rows 4 g + v of block bi and column li of block bj.
-template <int P, int R, int BI, int BJ, bool SQ = false>
+template <int P, int R, int BI, int BJ, bool SQ = false, bool RMW = false>
 __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X,
                                                int lx, int NI, int NJ, const unsigned* __restrict__ lst,
                                                typename PT<P>::A* scr, int kbase,
-                                               typename PT<P>::A* __restrict__ part) {
+                                               typename PT<P>::A* __restrict__ part, bool accum) {
     typedef typename PT<P>::A A;
     typedef typename PT<P>::Acc Acc;
     typedef typename PT<P>::Frag Frag;
@@ -749,7 +770,7 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 #pragma unroll
                     for (int bj = 0; bj < BJ; ++bj) mma1(acc[bi][bj], a[bi], b[bj], e);
         }
-        dw_select<A, Acc, BI>(acc, scr, pf, ent, kbase, part);
+        dw_select<A, Acc, BI, DWP<P>, RMW>(acc, scr, pf, ent, kbase, part, accum);
     }
 }
 
@@ -766,10 +787,10 @@ __device__ __forceinline__ void dw_dense_units(const typename PT<P>::T* D, int l
 // (i0 + 16 g + 4 v + bi, j0 + 2 li + bj); unit u = (i0 / 64) * NJ32 + j0 / 32.
 // Requires the padded output width to be a multiple of 64 and R a multiple
 // of 32 (the padded input width is a multiple of 32 for BF16).
-template <int R>
+template <int R, bool RMW = false>
 __device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf16* X, int lx, int NI64, int NJ32,
                                             const unsigned* __restrict__ lst, float* scr, int kbase,
-                                            float* __restrict__ part) {
+                                            float* __restrict__ part, bool accum) {
     typedef __bf16 b2v __attribute__((ext_vector_type(2)));
     static_assert(R % 32 == 0, "K chunks of 32 tile rows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -807,7 +828,7 @@ __device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf1
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) mma1(acc[bi][bj], fa[bi], fb[bj], 0);
         }
-        dw_select<float, f4v, 4>(acc, scr, pf, ent, kbase, part);
+        dw_select<float, f4v, 4, DWP<2>, RMW>(acc, scr, pf, ent, kbase, part, accum);
     }
 }
 
@@ -815,22 +836,23 @@ __device__ __forceinline__ void dw_dense_il(const __bf16* D, int ld, const __bf1
 // (its selection list is laid out for it): 2 x 2 blocks per unit, 4 x 2
 // blocks (BF16 and split BF16 layers wide enough for every wave), or the
 // interleaved 4 x 2 BF16 unit.
-template <int P, int R, bool SQ = false>
+template <int P, int R, bool SQ = false, bool RMW = false>
 __device__ __forceinline__ void dw_dense(const typename PT<P>::T* D, int ld, const typename PT<P>::T* X, int lx,
                                          int NI, int NJ, int variant, const unsigned* lst, typename PT<P>::A* scr,
-                                         int kbase, typename PT<P>::A* part) {
+                                         int kbase, typename PT<P>::A* part, bool accum) {
     if constexpr (R % PT<P>::KCH == 0) {
         if constexpr (P >= 2) {
             if (variant == DWV_IL) {
-                if constexpr (P == 2 && !SQ) dw_dense_il<R>(D, ld, X, lx, NI / 4, NJ / 2, lst, scr, kbase, part);
+                if constexpr (P == 2 && !SQ)
+                    dw_dense_il<R, RMW>(D, ld, X, lx, NI / 4, NJ / 2, lst, scr, kbase, part, accum);
                 return;
             }
             if (variant == DWV_4X2) {
-                dw_dense_units<P, R, 4, 2, SQ>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part);
+                dw_dense_units<P, R, 4, 2, SQ, RMW>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part, accum);
                 return;
             }
         }
-        dw_dense_units<P, R, 2, 2, SQ>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part);
+        dw_dense_units<P, R, 2, 2, SQ, RMW>(D, ld, X, lx, NI, NJ, lst, scr, kbase, part, accum);
     }
 }
 
@@ -895,17 +917,21 @@ __device__ __forceinline__ void ulik_store(double* slot8, double v) {
 // terms (sensitivity pass).  With tp.rc1 slab 1 shares its LDS with slab 3,
 // which the forward pass wrote later, so a_1 is recomputed from the input
 // (layer 0's tile product and tanh) once layer 2's adjoint no longer needs
-// slab 3.
-template <int P, int R, bool SQ = false>
-__device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, const TileMeta* m, int t,
+// slab 3.  slot: the partial slot of the tile (its row tile, or the
+// workgroup's tile group); accum: add to what the slot holds (a later tile
+// of the group; each entry's slot is read and written by the same thread
+// in every tile) instead of overwriting it, in instances with RMW (without
+// it the accumulating paths compile out).
+template <int P, int R, bool SQ = false, bool RMW = false>
+__device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPlan& tp, const TileMeta* m, int slot,
                                                const typename PT<P>::T* W, const typename PT<P>::A* B,
-                                               typename PT<P>::T* sm, int lowest) {
+                                               typename PT<P>::T* sm, int lowest, bool accum = false) {
     typedef typename PT<P>::A A;
     const long long o = m->o;
     const int n = m->n;
     const int* code = a.ecode + o;
     const int* seg = m->seg;
-    A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)t * n;
+    A* part = reinterpret_cast<A*>(a.part) + a.tmax * o + (long long)slot * n;
     const int* bseg = m->bseg;
     const unsigned dmask = m->dmask;
     for (int l = tp.nl - 1; l >= lowest; --l) {
@@ -922,13 +948,13 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
         }
         if (dmask & (1u << l)) {
             A* scr = reinterpret_cast<A*>(reinterpret_cast<unsigned char*>(sm) + tp.scr + (threadIdx.x >> 6) * 4096);
-            dw_dense<P, R, SQ>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.wp[l + 1] >> 4,
-                               tp.wp[l] >> 4, tp.dwv[l], a.ml + m->mloff[l], scr, seg[l], part);
-            dw_partials<P, R, SQ>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
-                                  part);
+            dw_dense<P, R, SQ, RMW>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.wp[l + 1] >> 4,
+                               tp.wp[l] >> 4, tp.dwv[l], a.ml + m->mloff[l], scr, seg[l], part, accum);
+            dw_partials<P, R, SQ, RMW>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
+                                       tp.ls[l], part, accum);
         } else {
-            dw_partials<P, R, SQ>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l],
-                                  part);
+            dw_partials<P, R, SQ, RMW>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
+                                       tp.ls[l], part, accum);
         }
         if (l > lowest) {
             __syncthreads();
@@ -1000,32 +1026,21 @@ template <int P, int R> constexpr int MLP_WAVES = (P == 1 && R == 64) ? 4 : 1;
 // ---------------------------------------------------------------------------
 // MLP: forward, head and adjoint of one (chain, row tile).
 // FWD = true: forward pass and likelihood partials only (the energy pass),
-// with activation slabs that may alias (ping-pong plans).
-template <int P, int R, bool FWD>
-__global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVES<P, R>))) void k_mlp_grad(
-    const GradArgs a) {
-    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* sm = reinterpret_cast<T*>(smem);
-    int c, t;
-    if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
-    if (!a.active[c]) return;
+// with activation slabs that may alias (ping-pong plans).  The biases and
+// the chain's tables are staged and published by the caller's first
+// barrier; slot and accum as in tower_backward.
+template <int P, int R, bool FWD, bool GROUP>
+__device__ __forceinline__ void mlp_tile(const GradArgs& a, int c, int t, int slot, bool accum,
+                                         const typename PT<P>::T* W, const typename PT<P>::A* B,
+                                         const TileMeta* meta, typename PT<P>::T* sm, double* ys) {
+    typedef typename PT<P>::T T;
     const TowerPlan& tp = a.ta;
-    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
-    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
     const int L = tp.nl - 1;
-    // biases and the tile's targets into LDS, beside the input rows
-    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
-    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
-    double* ys = reinterpret_cast<double*>(smem + a.y_lds);
     {
         const int nv = max(0, min(R, a.n_rows_a - t * R)) * a.d_out;
         const double* yg = a.target + (size_t)t * R * a.d_out;
         for (int i = threadIdx.x; i < R * a.d_out; i += blockDim.x) ys[i] = i < nv ? yg[i] : 0.0;
     }
-    const A* B = Bs - tp.bo[0];
-    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + a.meta_lds_a);
-    if constexpr (!FWD) stage_meta(a, tp, c, meta);
     load_rows<T, R>(sm + tp.lo[0], tp.ls[0], reinterpret_cast<const T*>(a.xa) + (size_t)t * R * tp.wp[0], tp.wp[0]);
     __syncthreads();
     const int lowest = FWD ? tp.nl : lowest_layer(tp, meta);
@@ -1047,7 +1062,48 @@ __global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVE
     ulik_store(a.ulik + ((size_t)c * a.tiles_a + t) * 8, 0.5 * a.inv_lik_var * sq);
     if constexpr (!FWD) {
         __syncthreads();
-        tower_backward<P, R>(a, tp, meta, t, W, B, sm, lowest);
+        tower_backward<P, R, false, GROUP>(a, tp, meta, slot, W, B, sm, lowest, accum);
+    }
+}
+
+// One (chain, row tile) per workgroup; GROUP: a workgroup takes a.tpg
+// consecutive row tiles of one chain and sums their weight-gradient terms
+// in tile order into one partial slot (each entry's slot read and written
+// by the thread that owns the entry), so that k_update reads a.tpg times
+// fewer partials.  The loop keeps more values live, so it is a separate
+// instance, used where it pays (the engine decides; tile_group).
+template <int P, int R, bool FWD, bool GROUP = false>
+__global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVES<P, R>))) void k_mlp_grad(
+    const GradArgs a) {
+    typedef typename PT<P>::T T; typedef typename PT<P>::A A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    const int tpg = GROUP ? a.tpg : 1;
+    const int groups = GROUP ? (a.tiles_a + tpg - 1) / tpg : a.tiles_a;
+    int c, grp;
+    if (!tile_of(a.n_chains * groups, groups, c, grp)) return;
+    if (!a.active[c]) return;
+    const TowerPlan& tp = a.ta;
+    const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
+    const A* Bg = reinterpret_cast<const A*>(a.bbuf) + c * a.bstride;
+    const int L = tp.nl - 1;
+    // biases into LDS beside the input rows (the tile's targets: mlp_tile)
+    A* Bs = reinterpret_cast<A*>(smem + a.bias_lds_a);
+    stage(Bs, Bg + tp.bo[0], (int)(tp.bo[L] + tp.wp[L + 1] - tp.bo[0]));
+    double* ys = reinterpret_cast<double*>(smem + a.y_lds);
+    const A* B = Bs - tp.bo[0];
+    TileMeta* meta = reinterpret_cast<TileMeta*>(smem + a.meta_lds_a);
+    if constexpr (!FWD) stage_meta(a, tp, c, meta);
+    if constexpr (GROUP) {
+        const int t0 = grp * tpg, t1 = min(a.tiles_a, t0 + tpg);
+        for (int t = t0; t < t1; ++t) {
+            mlp_tile<P, R, FWD, true>(a, c, t, grp, t > t0, W, B, meta, sm, ys);
+            // every read of this tile's slabs and targets is done before
+            // the next tile's rows and targets overwrite them
+            if (t + 1 < t1) __syncthreads();
+        }
+    } else {
+        mlp_tile<P, R, FWD, false>(a, c, grp, grp, false, W, B, meta, sm, ys);
     }
 }
 
@@ -1713,6 +1769,9 @@ template <int P, int R>
 hipError_t set_lds(size_t lds) {
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    if constexpr (P == 1 && R == 32) {   // the tile-group instance
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, 32, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+    }
     if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_trunk_bwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
@@ -1855,6 +1914,11 @@ hipError_t hmc_set_lds_limit(int P, int R, size_t lds) {
 // nt: threads per workgroup, 256 or 512 (the tile kernels are written for
 // any multiple of 64 up to HMC_NT).
 hipError_t hmc_launch_mlp_grad(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {
+    if (a.tpg > 1) {   // tile groups: instantiated for FP32 products at 32 rows (tile_group)
+        if (P != 1 || R != 32) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_mlp_grad<1, 32, false, true>), dim3(grid), dim3(nt), lds, s, a);
+        return hipGetLastError();
+    }
     HMC_DISPATCH_PR(P, R, HMC_TILE_CALL_k_mlp_grad)
 }
 hipError_t hmc_launch_trunk_fwd(int P, int R, int nt, const GradArgs& a, int grid, size_t lds, hipStream_t s) {

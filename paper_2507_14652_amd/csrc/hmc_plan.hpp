@@ -62,6 +62,8 @@ struct GradArgs {
     int n_rows_b;               // valid rows of the trunk (n_q)
     int d_out;                  // MLP output width
     int tiles_a, tiles_b;
+    int tpg;                    // row tiles per workgroup of the MLP gradient kernel, whose
+                                // weight-gradient terms it sums into one partial slot
     int n_chains;
     const int* active;          // [C]
     const long long* offs;      // [C+1]
@@ -77,7 +79,7 @@ struct GradArgs {
                                 //   first entry, LDS scratch slot) as uint2
     const long long* ml_off;    // [C][nl_total] word offset of a (chain, layer) block in ml (-1: none)
     void* part;                 // per-tile gradient partials, A
-    long long tmax;             // tiles per chain in the partial layout
+    long long tmax;             // partial slots per chain in the partial layout
     double* ulik;               // [C][tiles_a][8] likelihood partials (one slot per wave)
     double inv_lik_var;
     // DeepONet exchange buffers, T
@@ -108,7 +110,7 @@ struct StateArgs {
     const int* seg;
     int nseg;
     int seg_trunk_lo, seg_trunk_hi;   // segment indices bounding the trunk entries
-    int tiles_a, tiles_b;
+    int tiles_a, tiles_b;       // partial slots per chain and tower (row tiles, or tile groups)
     long long tmax;
     const void* part;
     const double* ulik;         // likelihood partials that define U, [C][ulik_tiles][8]

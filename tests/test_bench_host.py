@@ -62,3 +62,11 @@ def test_split_ess_sees_a_drift_inside_one_chain():
     assert np.all(np.abs(bench.split_ess(x) / 4000 - 1) < 0.15)
     x += np.linspace(0.0, 6.0, 4000)[:, None]     # a trend the chain has not left
     assert np.all(bench.split_ess(x) < 100)
+
+
+def test_energy_pass_instances_are_told_apart():
+    assert bench.energy_pass("void (anonymous namespace)::k_mlp_grad<1, 32, true, false>(GradArgs)")
+    assert bench.energy_pass("void (anonymous namespace)::k_branch_grad<1, 64, true>(GradArgs)")
+    assert not bench.energy_pass("void (anonymous namespace)::k_mlp_grad<1, 32, false, true>(GradArgs)")
+    assert not bench.energy_pass("void (anonymous namespace)::k_branch_grad<3, 32, false>(GradArgs)")
+    assert not bench.energy_pass("void (anonymous namespace)::k_update<1>(StateArgs, int, int)")
