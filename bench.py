@@ -9,9 +9,13 @@ gradient evaluations per second summed over chains.
 Prints one JSON line.  The default workload is the largest single-GPU
 configuration, the batched uneven chains: 256 chains on the MLP
 4-256-256-256-256-1 tanh over 16,384 rows, each chain sampling its own 1% to
-20% of the parameters, BF16 products, L = 50, per-chain step sizes adapted
-on the device to 80% acceptance before the timed region; --config selects
-another named workload.
+20% of the parameters, L = 50, per-chain step sizes adapted on the device
+toward 80% acceptance before the timed region.  Each workload samples in the
+product precision whose Metropolis decisions match FP64 ones on it (FP32
+here; the line names it); --config selects another named workload and
+--precision another precision.  The line also carries the roofline of the
+dominant kernel, the FP64 oracle timed on the host cores, and the ESS/s
+comparison with plain single-chain FP32 HMC on the DeepONet workload.
 """
 
 from __future__ import annotations
