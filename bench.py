@@ -76,16 +76,17 @@ def algorithmic_flops(w, part=None):
     return total
 
 
-def recorded_traffic(kernel, workload, template=None):
+def recorded_traffic(kernel, workload, instance=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy), or None
     when the kernel source has changed since the counters were taken or they
-    were taken on another instance (template: its name prefix)."""
+    were taken on another instance (instance: the prefix of its name, up to
+    the tile height)."""
     p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_sha256") != _kernel_sha() or (template and d.get("template") != template):
+    if d.get("kernel_source_sha256") != _kernel_sha() or (instance and not d.get("instance", "").startswith(instance)):
         return None
     return d["traffic_bytes_per_launch"]
 
@@ -136,15 +137,18 @@ def _pmc_mean(csv_path, counter, name_part):
     Gradient kernels count only in their gradient form, not as the
     forward-only energy pass."""
     import csv
-    vals = []
+    vals, names = [], set()
     with open(csv_path) as f:
         for r in csv.DictReader(f):
             k = r["Kernel_Name"]
             if r["Counter_Name"] == counter and name_part in k and not energy_pass(k):
                 vals.append(float(r["Counter_Value"]))
+                names.add(k.replace("void (anonymous namespace)::", ""))
     if not vals:
         raise SystemExit(f"no {counter} rows for {name_part} in {csv_path}")
-    return sum(vals) / len(vals), len(vals)
+    if len(names) != 1:
+        raise SystemExit(f"{counter}: several instances match {name_part}: {sorted(names)}")
+    return sum(vals) / len(vals), len(vals), names.pop()
 
 
 def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
@@ -157,13 +161,15 @@ def record_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_di
     kern = KERNEL_OF[w.kind]
     main = main_kernel(w)
     one = lambda d: glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
-    fk, nd = _pmc_mean(one(fetch_dir), "FETCH_SIZE", main)
-    wk, _ = _pmc_mean(one(write_dir), "WRITE_SIZE", main)
-    cf, _ = _pmc_mean(one(copy_fetch_dir), "FETCH_SIZE", "copy")
-    cw, _ = _pmc_mean(one(copy_write_dir), "WRITE_SIZE", "copy")
+    fk, nd, inst = _pmc_mean(one(fetch_dir), "FETCH_SIZE", main)
+    wk, _, inst_w = _pmc_mean(one(write_dir), "WRITE_SIZE", main)
+    assert inst == inst_w, (inst, inst_w)
+    cf, _, _ = _pmc_mean(one(copy_fetch_dir), "FETCH_SIZE", "copy")
+    cw, _, _ = _pmc_mean(one(copy_write_dir), "WRITE_SIZE", "copy")
     ff, wf = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
     out = {
-        "kernel": kern, "template": main, "workload": workload, "kernel_source_sha256": _kernel_sha(),
+        "kernel": kern, "template": main, "instance": inst, "workload": workload,
+        "kernel_source_sha256": _kernel_sha(),
         "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "dispatches": nd,
         "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
                              "fetch_factor": ff, "write_factor": wf},
@@ -797,7 +803,7 @@ def main():
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAK[DTYPE[w.precision]]
     kname = KERNEL_OF[w.kind]
-    traffic = recorded_traffic(kname, w.name, f"{kname}<{PRECISION_INDEX[w.precision]}, ")
+    traffic = recorded_traffic(kname, w.name, f"{kname}<{PRECISION_INDEX[w.precision]}, {s.info['rows_per_tile_a']}, ")
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "kernel": kname, "kernel_ms": dom_ms, "flops_per_launch": flops,
             "hbm_gbps": traffic / (dom_ms * 1e-3) / 1e9 if traffic else None}
