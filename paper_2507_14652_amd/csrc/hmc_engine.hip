@@ -363,12 +363,13 @@ int pick_rows_energy(const TowerPlan& src, size_t fixed, size_t per_row, size_t 
 // scr_bytes: the dense weight-gradient scratch, needed at tile heights that
 // are multiples of kch.
 int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t fixed, long long rows, int chains,
-              const char* env, int forced, size_t scr_bytes, int kch, bool& alias) {
+              const char* env, int forced, size_t scr_bytes, int kch, bool& alias, bool pair = false) {
     alias = false;
-    auto fits_as = [&](int r, bool al) {
+    auto bytes_as = [&](int r, bool al) {
         const size_t scr = r % kch == 0 ? scr_bytes : 0;
-        return tower_lds(w, prec, r, al) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed + scr <= g_lds_cap;
+        return tower_lds(w, prec, r, al) + extra_per_row * r + 64 + HMC_META_BYTES + 16 + fixed + scr;
     };
+    auto fits_as = [&](int r, bool al) { return bytes_as(r, al) <= g_lds_cap; };
     const char* rc = std::getenv("HMC_RECOMPUTE");   // "1": share wherever possible (tests)
     const bool force_alias = rc && !std::strcmp(rc, "1");
     // the sharing choice for one candidate height; false: it does not fit
@@ -391,6 +392,17 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
         best /= 2;
         alias = al2;
     }
+    // pair: on a large grid take 16-row tiles when two of those fit in one
+    // compute unit's LDS and one of 32 rows does not (the FP32 MLP kernel:
+    // two resident workgroups hide its LDS and barrier latency better than
+    // one of twice the height; 256-wide MLP, 256 chains: 72.3 + 4.0 ms per
+    // gradient evaluation at 16 rows against 78.9 + 0.25 at 32 with tile
+    // groups)
+    if (pair && best == 32 && bytes_as(32, alias) > g_lds_cap / 2 && choose(16, al2) &&
+        bytes_as(16, al2) <= g_lds_cap / 2 && (long long)chains * ((rows + 15) / 16) >= 16 * 256) {
+        best = 16;
+        alias = al2;
+    }
     return best;
 }
 
@@ -401,9 +413,10 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
 // eight while the grid keeps at least 16 workgroups per compute unit, for
 // FP32 products at 32-row tiles only, where the read-modify-writes cost
 // the gradient kernel nothing measurable (256-chain MLP: 79.7 against
-// 79.7 ms, k_update 1.91 -> 0.25 ms); at 16-row tiles they cost it 9%
-// (71.6 -> 78.3 ms, two resident workgroups per compute unit), and the
-// loop's registers cost a third of the BF16 kernel.
+// 79.7 ms, k_update 1.91 -> 0.25 ms); the 16-row instance ran 77.1 ms
+// against 72.3 ungrouped (two resident workgroups per compute unit), more
+// than k_update saves, and the loop's registers cost a third of the BF16
+// kernel.
 // HMC_TILE_GROUP (1, 2, 4 or 8) overrides the size where groups apply.
 int tile_group(int prec, int R, int chains, int tiles) {
     if (prec != HMC_FP32 || R != 32) return 1;
@@ -556,7 +569,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     if (x->kind == HMC_MLP) {
         rows_a = data->n_rows;
         x->Ra = pick_rows(x->A.w, prec, (size_t)x->A.w.back() * 8, bias_bytes(x->A.w, prec, as), rows_a, x->C,
-                          "HMC_ROWS_A", x->tune.rows_a, scr_a, kch, x->alias_a);
+                          "HMC_ROWS_A", x->tune.rows_a, scr_a, kch, x->alias_a, prec == HMC_FP32 && !x->force_dense);
     } else {
         rows_a = data->n_u;
         rows_b = data->n_q;

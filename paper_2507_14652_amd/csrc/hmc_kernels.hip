@@ -591,6 +591,43 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
     int lpe = 1;
     while (lpe < 16 && 2 * lpe <= R && n * 2 * lpe <= nthr) lpe *= 2;
     if (lpe == 1) {
+        if constexpr (RMW) {
+            if (accum) {
+                // adding to the running sums of the workgroup's earlier tiles
+                // (this thread wrote them): four of the thread's entries at a
+                // time, their codes and running sums loaded together, so that
+                // the latency of those loads (from L2 or memory) is paid once
+                // per four entries
+                for (int kb = k0 + (int)threadIdx.x; kb < k1; kb += 4 * nthr) {
+                    int cd[4];
+                    A s[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = kb + q * nthr;
+                        cd[q] = k < k1 ? code[k] : 0;
+                        s[q] = k < k1 ? part[k] : (A)0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = kb + q * nthr;
+                        if (k < k1) {
+                            const int i = cd[q] >> 16, j = cd[q] & 0xFFFF;
+                            if (j == 0xFFFF) {
+#pragma unroll 8
+                                for (int r = 0; r < R; ++r) s[q] += sq_if<SQ>(ld1<P>(D + r * ld, i));
+                            } else {
+#pragma unroll 8
+                                for (int r = 0; r < R; ++r)
+                                    s[q] = fma(sq_if<SQ>(ld1<P>(D + r * ld, i)), sq_if<SQ>(ld1<P>(X + r * lx, j)),
+                                               s[q]);
+                            }
+                            part[k] = s[q];
+                        }
+                    }
+                }
+                return;
+            }
+        }
         // the code of the thread's next entry is loaded while this one sums,
         // so that its global latency is paid once, not once per pass
         int cn = k0 + (int)threadIdx.x < k1 ? code[k0 + threadIdx.x] : 0;
@@ -598,10 +635,7 @@ __device__ __forceinline__ void dw_partials(const int* __restrict__ code, int k0
             const int cd = cn;
             if (k + nthr < k1) cn = code[k + nthr];
             const int i = cd >> 16, j = cd & 0xFFFF;
-            // the running sum of the workgroup's earlier tiles (this thread
-            // wrote it), loaded before the sum so that its latency overlaps it
             A s = (A)0;
-            if constexpr (RMW) s = accum ? part[k] : (A)0;
             if (j == 0xFFFF) {
 #pragma unroll 8
                 for (int r = 0; r < R; ++r) s += sq_if<SQ>(ld1<P>(D + r * ld, i));
@@ -1770,7 +1804,7 @@ hipError_t set_lds(size_t lds) {
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if constexpr (P == 1 && R == 32) {   // the tile-group instance
-        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, 32, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_mlp_grad<1, R, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     }
     if ((e = hipFuncSetAttribute((const void*)k_trunk_fwd<P, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_branch_grad<P, R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))) return e;
