@@ -801,10 +801,10 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     }
     // Per layer: where its bias entries start, and whether its weight partials
     // come from a dense tile product (MFMA over the tile rows, selected
-    // entries picked through the layer's selection bitmap) or from per-entry
-    // sums (two LDS reads and one FMA per row and entry).  Per tile, the
-    // dense product costs in proportion to in*out (mostly the selection
-    // through the bitmap, whatever the tile height), the sums in proportion
+    // entries copied out through the layer's selection list) or from
+    // per-entry sums (two LDS reads and one FMA per row and entry).  Per
+    // tile, the dense product costs in proportion to in*out (the product and
+    // the scratch writes, whatever the tile height), the sums in proportion
     // to (selected count) * R.  Measured on MI355X: in BF16 (MFMA 16x faster
     // than FP32) the dense product halves the 256-wide MLP at 1-20% density
     // (R = 64) and is faster on the 128-wide DeepONet branch at 5% (R = 64,
