@@ -158,7 +158,7 @@ typedef struct {
     int32_t kind;
     int32_t rows_per_tile_a;  /* rows of the MLP / branch tiles              */
     int32_t rows_per_tile_b;  /* rows of the trunk tiles (DeepONet)          */
-    int32_t tiles_a;
+    int32_t tiles_a;          /* row tiles of the MLP / branch tower         */
     int32_t tiles_b;
     int64_t device_bytes;     /* device memory held by the engine            */
     int32_t threads_a;        /* threads per workgroup of the MLP / branch   */
@@ -183,7 +183,11 @@ hmc_status hmc_init(hmc_ctx** out, const hmc_net_desc* net, const hmc_mask_desc*
  * the summation order); 0 in a field keeps the
  * engine's own choice (made from the LDS footprint, the grid size and the
  * layer densities; HMC_ROWS_A, HMC_ROWS_B, HMC_THREADS and HMC_DW in the
- * environment override it when the field is 0). */
+ * environment override it when the field is 0).  FP32 MLP engines at
+ * 32-row tiles on large grids also let one workgroup sum several row tiles
+ * of a chain into one partial slot (HMC_TILE_GROUP = 1, 2, 4 or 8 fixes the
+ * number); the result differs from one tile per workgroup only in the
+ * summation order. */
 typedef struct {
     int32_t rows_a;    /* rows per tile of the MLP / branch tower: 0, 16, 32 or 64       */
     int32_t rows_b;    /* rows per tile of the trunk tower: 0, 16, 32 or 64              */
