@@ -953,6 +953,12 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     g.seg = seg_d;
     g.nseg = nseg;
     g.tpg = x->tpg;
+    {
+        // adjoint layers: weight gradient beside the adjoint product's
+        // multiplies (HMC_OVERLAP=0 runs them one after the other)
+        const char* ov = std::getenv("HMC_OVERLAP");
+        g.overlap = ov && !std::strcmp(ov, "0") ? 0 : 1;
+    }
     g.tmax = std::max(x->groups_a, x->tiles_b);
     g.part = x->dalloc((size_t)g.tmax * x->nnz * as);
     g.ulik = (double*)x->dalloc(sizeof(double) * 8 * x->C * x->tiles_a);

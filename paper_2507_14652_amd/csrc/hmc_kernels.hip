@@ -31,6 +31,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hmc_launch.hpp"
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -234,6 +236,66 @@ __device__ __forceinline__ int nrb_of(int Np) {
     return NB * 2 >= nwave ? R / 16 : 1;
 }
 
+// One group of four K chunks of a work unit: the weight fragments ac[q]
+// (chunk q) times the LDS operand rows at xg (row stride ldx), MFMAs
+// element-major over independent accumulators (the NRB row blocks, or with
+// one row block the four chunk accumulators); the LDS fragments of chunk
+// q + 1 are read while chunk q multiplies.
+template <int P, int NRB, int KS>
+__device__ __forceinline__ void gemm_group(typename PT<P>::Acc (&acc)[NRB][KS], const typename PT<P>::Frag (&ac)[4],
+                                           const typename PT<P>::T* xg, int ldx) {
+    typedef typename PT<P>::Frag Frag;
+    constexpr int KCH = PT<P>::KCH;
+    if constexpr (NRB == 1) {
+        Frag b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = *reinterpret_cast<const Frag*>(xg + q * KCH);
+#pragma unroll
+        for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mma1(acc[0][q], ac[q], b[q], e);
+    } else {
+        Frag bA[NRB], bB[NRB];
+        auto loadB = [&](Frag (&b)[NRB], int q) {
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) b[i] = *reinterpret_cast<const Frag*>(xg + (size_t)i * 16 * ldx + q * KCH);
+        };
+        auto mul = [&](const Frag (&b)[NRB], const Frag& aq) {
+#pragma unroll
+            for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+                for (int i = 0; i < NRB; ++i) mma1(acc[i][0], aq, b[i], e);
+        };
+        loadB(bA, 0);
+        loadB(bB, 1);
+        mul(bA, ac[0]);
+        loadB(bA, 2);
+        mul(bB, ac[1]);
+        loadB(bB, 3);
+        mul(bA, ac[2]);
+        mul(bB, ac[3]);
+    }
+}
+
+// The K % (4 chunks) remainder of a work unit: chunk by chunk from weight
+// row wr and operand rows xr (both at the remainder's first column).
+template <int P, int NRB, int KS>
+__device__ __forceinline__ void gemm_rem(typename PT<P>::Acc (&acc)[NRB][KS], const typename PT<P>::T* wr,
+                                         const typename PT<P>::T* xr, int ldx, int rem) {
+    typedef typename PT<P>::Frag Frag;
+    constexpr int KCH = PT<P>::KCH;
+    for (int c = 0; c < rem; ++c) {
+        const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
+        Frag b[NRB];
+#pragma unroll
+        for (int i = 0; i < NRB; ++i) b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + c * KCH);
+#pragma unroll
+        for (int e = 0; e < NE<P>; ++e)
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) mma1(acc[i][0], a, b[i], e);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Tile product: for n in [0, Np) and r in [0, R)
 //     out^T[n][r] = sum_{k < K} Wm[n][k] * X[r][k]
@@ -296,59 +358,13 @@ __device__ __forceinline__ void gemm_units(const typename PT<P>::T* __restrict__
 #pragma unroll
                 for (int q = 0; q < 4; ++q) an[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
             }
-            const T* xg = xr + grp * GK;
-            // MFMAs element-major over independent accumulators (the NRB row
-            // blocks, or with one row block the four chunk accumulators); the
-            // LDS fragments of chunk q + 1 are read while chunk q multiplies
-            if constexpr (NRB == 1) {
-                Frag b[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) b[q] = *reinterpret_cast<const Frag*>(xg + q * KCH);
-#pragma unroll
-                for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) mma1(acc[0][q], ac[q], b[q], e);
-            } else {
-                Frag bA[NRB], bB[NRB];
-                auto loadB = [&](Frag (&b)[NRB], int q) {
-#pragma unroll
-                    for (int i = 0; i < NRB; ++i)
-                        b[i] = *reinterpret_cast<const Frag*>(xg + (size_t)i * 16 * ldx + q * KCH);
-                };
-                auto mul = [&](const Frag (&b)[NRB], const Frag& aq) {
-#pragma unroll
-                    for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                        for (int i = 0; i < NRB; ++i) mma1(acc[i][0], aq, b[i], e);
-                };
-                loadB(bA, 0);
-                loadB(bB, 1);
-                mul(bA, ac[0]);
-                loadB(bA, 2);
-                mul(bB, ac[1]);
-                loadB(bB, 3);
-                mul(bA, ac[2]);
-                mul(bB, ac[3]);
-            }
+            gemm_group<P, NRB, KS>(acc, ac, xr + grp * GK, ldx);
 #pragma unroll
             for (int q = 0; q < 4; ++q) ac[q] = an[q];
         }
         if (grp == gpu - 1) {
             // remaining K % GK chunks of the unit, then its epilogue
-            if (rem) {
-                const T* wr = wrow(ui) + ng * GK;
-                for (int c = 0; c < rem; ++c) {
-                    const Frag a = *reinterpret_cast<const Frag*>(wr + c * KCH);
-                    Frag b[NRB];
-#pragma unroll
-                    for (int i = 0; i < NRB; ++i)
-                        b[i] = *reinterpret_cast<const Frag*>(xr + (size_t)i * 16 * ldx + ng * GK + c * KCH);
-#pragma unroll
-                    for (int e = 0; e < NE<P>; ++e)
-#pragma unroll
-                        for (int i = 0; i < NRB; ++i) mma1(acc[i][0], a, b[i], e);
-                }
-            }
+            if (rem) gemm_rem<P, NRB, KS>(acc, wrow(ui) + ng * GK, xr + ng * GK, ldx, rem);
 #pragma unroll
             for (int i = 0; i < NRB; ++i) {
                 Acc t = acc[i][0];
@@ -373,6 +389,98 @@ __device__ __forceinline__ void gemm(const typename PT<P>::T* Wm, int ldw, int K
         }
     }
     gemm_units<P, R, 1>(Wm, ldw, K, Np, X, ldx, epi);
+}
+
+// Deferred tile product: the wave's work units (at most MAXU of them, the
+// caller checks) multiplied into dacc with the arithmetic of gemm_units in
+// the same order, the epilogues later (gemm_deferred_epi), so that other
+// work can run between the two.  NRB as gemm() picks it.
+template <int P, int R, int NRB>
+__device__ __forceinline__ int deferred_units(int Np) {
+    constexpr int RG = (R / 16) / NRB;
+    const int wave = (int)(threadIdx.x >> 6), nwave = (int)(blockDim.x >> 6);
+    const int units = (Np >> 4) * RG;
+    return units > wave ? (units - wave + nwave - 1) / nwave : 0;
+}
+// ... and the most any wave of the workgroup takes (wave 0's count): the
+// same in every wave, so a branch on it keeps the workgroup together
+template <int P, int R, int NRB>
+__device__ __forceinline__ int deferred_units_max(int Np) {
+    constexpr int RG = (R / 16) / NRB;
+    const int nwave = (int)(blockDim.x >> 6);
+    return ((Np >> 4) * RG + nwave - 1) / nwave;
+}
+template <int P, int R, int NRB, int MAXU>
+__device__ __forceinline__ void gemm_deferred(const typename PT<P>::T* __restrict__ Wm, int ldw, int K, int Np,
+                                              const typename PT<P>::T* X, int ldx,
+                                              typename PT<P>::Acc (&dacc)[MAXU][NRB]) {
+    typedef typename PT<P>::T T;
+    typedef typename PT<P>::Acc Acc;
+    typedef typename PT<P>::Frag Frag;
+    constexpr int KCH = PT<P>::KCH, VEC = PT<P>::VEC;
+    constexpr int GK = 4 * KCH;
+    constexpr int RG = (R / 16) / NRB;
+    constexpr int KS = NRB == 1 ? 4 : 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (int)(blockDim.x >> 6);
+    const int g = lane >> 4, li = lane & 15;
+    const int arow = (P == 0) ? (4 * (li & 3) + (li >> 2)) : li;
+    const int my_units = deferred_units<P, R, NRB>(Np);
+    const int ng = K / GK;
+    const int rem = (K - ng * GK) / KCH;
+#pragma unroll
+    for (int ui = 0; ui < MAXU; ++ui) {
+        if (ui < my_units) {
+            const int u = wave + ui * nwave;
+            const int nb = u / RG, rg = u - nb * RG;
+            const T* wr = Wm + (size_t)(nb * 16 + arow) * ldw + g * VEC;
+            const T* xr = X + (size_t)(rg * NRB * 16 + li) * ldx + g * VEC;
+            Acc acc[NRB][KS];
+#pragma unroll
+            for (int i = 0; i < NRB; ++i)
+#pragma unroll
+                for (int q = 0; q < KS; ++q) acc[i][q] = Acc{};
+            Frag ac[4], an[4];
+            if (ng > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ac[q] = *reinterpret_cast<const Frag*>(wr + q * KCH);
+            }
+            for (int grp = 0; grp < ng; ++grp) {
+                if (grp + 1 < ng) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) an[q] = *reinterpret_cast<const Frag*>(wr + (grp + 1) * GK + q * KCH);
+                }
+                gemm_group<P, NRB, KS>(acc, ac, xr + grp * GK, ldx);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ac[q] = an[q];
+            }
+            if (rem) gemm_rem<P, NRB, KS>(acc, wr + ng * GK, xr + ng * GK, ldx, rem);
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) {
+                Acc t = acc[i][0];
+#pragma unroll
+                for (int q = 1; q < KS; ++q) t += acc[i][q];
+                dacc[ui][i] = t;
+            }
+        }
+    }
+}
+template <int P, int R, int NRB, int MAXU, class Epi>
+__device__ __forceinline__ void gemm_deferred_epi(int Np, const typename PT<P>::Acc (&dacc)[MAXU][NRB], Epi& epi) {
+    constexpr int RG = (R / 16) / NRB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwave = (int)(blockDim.x >> 6);
+    const int g = lane >> 4, li = lane & 15;
+    const int my_units = deferred_units<P, R, NRB>(Np);
+#pragma unroll
+    for (int ui = 0; ui < MAXU; ++ui) {
+        if (ui < my_units) {
+            const int u = wave + ui * nwave;
+            const int nb = u / RG, rg = u - nb * RG;
+#pragma unroll
+            for (int i = 0; i < NRB; ++i) epi((rg * NRB + i) * 16 + li, nb * 16 + 4 * g, dacc[ui][i]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -943,9 +1051,55 @@ __device__ __forceinline__ void ulik_store(double* slot8, double v) {
     if ((threadIdx.x & 63) == 0) slot8[threadIdx.x >> 6] = v;
 }
 
+// A layer of the adjoint pass with its weight-gradient terms (dw) and the
+// multiplies of its adjoint product in one phase: the product's epilogue,
+// which overwrites the layer input's slab with its adjoint, waits for a
+// barrier, so that neither needs the other's result and the waves of a
+// workgroup interleave the two (even waves multiply first, odd waves start
+// with dw), the product on the matrix cores while dw reads LDS.  The
+// arithmetic of both is that of the sequential order.  Returns false,
+// having done nothing, when a wave would hold more than two units'
+// accumulators (one with four row blocks; then the caller runs the two one
+// after the other).
+template <int P, int R, class DW>
+__device__ __forceinline__ bool back_overlap(const GradArgs& a, const TowerPlan& tp, const typename PT<P>::T* W,
+                                             typename PT<P>::T* sm, int l, DW& dw) {
+    typedef typename PT<P>::Acc Acc;
+    constexpr int RB = R / 16;
+    const int Np = tp.wp[l], K = tp.wp[l + 1];
+    const typename PT<P>::T* Wt = W + tp.wto[l];
+    const typename PT<P>::T* Xd = sm + tp.lo[l + 1];
+    const int ldx = tp.ls[l + 1];
+    const int odd = (int)(threadIdx.x >> 6) & 1;
+    EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};
+    auto run = [&](auto nrb) -> bool {
+        constexpr int NRB = decltype(nrb)::value;
+        constexpr int MAXU = NRB >= 4 ? 1 : 2;
+        if (deferred_units_max<P, R, NRB>(Np) > MAXU) return false;   // the same in every wave
+        Acc dacc[MAXU][NRB];
+        if (odd) {
+            dw();
+            gemm_deferred<P, R, NRB, MAXU>(Wt, K, K, Np, Xd, ldx, dacc);
+        } else {
+            gemm_deferred<P, R, NRB, MAXU>(Wt, K, K, Np, Xd, ldx, dacc);
+            dw();
+        }
+        __syncthreads();
+        gemm_deferred_epi<P, R, NRB, MAXU>(Np, dacc, e);
+        __syncthreads();
+        return true;
+    };
+    if constexpr (RB > 1) {
+        if (nrb_of<R>(Np) == RB) return run(std::integral_constant<int, RB>{});
+    }
+    return run(std::integral_constant<int, 1>{});
+}
+
 // Adjoint pass of one tower from the output adjoint held in slab nl: for each
 // layer from the top, the selected weight-gradient partials, then (while a
-// lower layer still has selected entries) the adjoint of the layer input.
+// lower layer still has selected entries) the adjoint of the layer input;
+// with a.overlap, at tiles of up to 32 rows, the two in one phase
+// (back_overlap).
 // m: the chain's tables (stage_meta, published); lowest: lowest_layer() of
 // the chain; B: the tower's biases (staged).  SQ: squared weight-gradient
 // terms (sensitivity pass).  With tp.rc1 slab 1 shares its LDS with slab 3,
@@ -980,16 +1134,26 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
                 __syncthreads();
             }
         }
-        if (dmask & (1u << l)) {
-            A* scr = reinterpret_cast<A*>(reinterpret_cast<unsigned char*>(sm) + tp.scr + (threadIdx.x >> 6) * 4096);
-            dw_dense<P, R, SQ, RMW>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.wp[l + 1] >> 4,
-                               tp.wp[l] >> 4, tp.dwv[l], a.ml + m->mloff[l], scr, seg[l], part, accum);
-            dw_partials<P, R, SQ, RMW>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
-                                       tp.ls[l], part, accum);
-        } else {
-            dw_partials<P, R, SQ, RMW>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
-                                       tp.ls[l], part, accum);
+        // this layer's weight-gradient terms: dense product or per-entry sums
+        auto weight_gradient = [&]() {
+            if (dmask & (1u << l)) {
+                A* scr = reinterpret_cast<A*>(reinterpret_cast<unsigned char*>(sm) + tp.scr + (threadIdx.x >> 6) * 4096);
+                dw_dense<P, R, SQ, RMW>(sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l], tp.ls[l], tp.wp[l + 1] >> 4,
+                                   tp.wp[l] >> 4, tp.dwv[l], a.ml + m->mloff[l], scr, seg[l], part, accum);
+                dw_partials<P, R, SQ, RMW>(code, bseg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
+                                           tp.ls[l], part, accum);
+            } else {
+                dw_partials<P, R, SQ, RMW>(code, seg[l], seg[l + 1], sm + tp.lo[l + 1], tp.ls[l + 1], sm + tp.lo[l],
+                                           tp.ls[l], part, accum);
+            }
+        };
+        // (64-row tiles run the two one after the other: holding the deferred
+        // accumulators beside their four row blocks spills the FP32 kernel
+        // that must stay within 128 registers, 33.4 -> 34.9 us on the 2-D MLP)
+        if constexpr (R <= 32) {
+            if (l > lowest && a.overlap && back_overlap<P, R>(a, tp, W, sm, l, weight_gradient)) continue;
         }
+        weight_gradient();
         if (l > lowest) {
             __syncthreads();
             EpiBack<P> e{sm + tp.lo[l], tp.ls[l]};

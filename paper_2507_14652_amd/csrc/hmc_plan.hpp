@@ -64,6 +64,8 @@ struct GradArgs {
     int tiles_a, tiles_b;
     int tpg;                    // row tiles per workgroup of the MLP gradient kernel, whose
                                 // weight-gradient terms it sums into one partial slot
+    int overlap;                // adjoint pass: a layer's weight gradient beside its adjoint
+                                // product's multiplies (epilogues after a barrier)
     int n_chains;
     const int* active;          // [C]
     const long long* offs;      // [C+1]
