@@ -16,7 +16,14 @@ Readings (the paper leaves these open):
   * r > u is decided as log u < H0 - H1 in FP64, u in the open interval
     (0, 1); a non-finite H1 is a rejected, divergent proposal (Sec. 4.2.3
     reports infinite gradients in full-batch runs);
-  * fixed step size, no jitter; M = I unless a diagonal inverse mass is given.
+  * fixed step size, no jitter; M = I unless a diagonal inverse mass is given;
+  * symmetric splitting (the integrator the paper's full-HMC baseline takes
+    from Cobb and Jalaian, whose algorithm the paper does not restate): the
+    potential is a sum of data-batch potentials, each with 1/M of the prior,
+    and a step applies their half kicks in batch order, one drift, then
+    their half kicks in the mirrored order.  The half kicks on either side of
+    the drift act at one position, so in exact arithmetic the step is the
+    leapfrog step; only the order in which batch gradients reach p differs.
 """
 
 from __future__ import annotations
@@ -52,6 +59,47 @@ def leapfrog(potential_and_grad, theta, p, eps, L, inv_mass=None, start=None):
         U, g = potential_and_grad(theta)
         p = p - (eps if t < L else 0.5 * eps) * g
     return theta, p, U, g
+
+
+def split_leapfrog(batch_potentials, theta, p, eps, L, inv_mass=None):
+    """L steps of symmetric-splitting HMC, the integrator of the paper's
+    full-HMC baseline (Sec. 4.2.3, after Cobb and Jalaian): with the
+    potential split over data batches, U = sum_m U_m, one step of size eps is
+    the half kicks -eps/2 grad U_m in batch order m = 1..M, one drift
+    eps M^-1 p, then the half kicks in the mirrored order m = M..1.  Every
+    batch gradient is evaluated where it is applied, at the position of that
+    half step (nothing is cached or merged).
+
+    ``batch_potentials``: the M callables theta -> (U_m, grad U_m).
+    Returns (theta_L, p_L, U_L, g_L) with U_L and g_L the sums over the
+    batches at theta_L."""
+    theta = np.array(theta, dtype=np.float64)
+    p = np.array(p, dtype=np.float64)
+    minv = 1.0 if inv_mass is None else np.asarray(inv_mass, dtype=np.float64)
+    for _ in range(L):
+        for f in batch_potentials:
+            p = p - 0.5 * eps * f(theta)[1]
+        theta = theta + eps * minv * p
+        for f in reversed(batch_potentials):
+            p = p - 0.5 * eps * f(theta)[1]
+    parts = [f(theta) for f in batch_potentials]
+    U = sum(u for u, _ in parts)
+    g = np.sum([gm for _, gm in parts], axis=0)
+    return theta, p, U, g
+
+
+def split_transition(batch_potentials, theta, U, p, eps, L, u, inv_mass=None):
+    """One iteration of Algorithm 2 with the symmetric-splitting integrator:
+    as ``transition``, the leapfrog replaced by ``split_leapfrog``."""
+    H0 = hamiltonian(U, p, inv_mass)
+    th1, p1, U1, g1 = split_leapfrog(batch_potentials, theta, p, eps, L, inv_mass)
+    H1 = hamiltonian(U1, p1, inv_mass)
+    acc = metropolis_accept(H0, H1, u)
+    stats = {"H0": H0, "H1": H1, "log_u": math.log(u), "accepted": acc,
+             "divergent": not math.isfinite(H1)}
+    if acc:
+        return th1, U1, g1, stats
+    return np.array(theta, dtype=np.float64), U, None, stats
 
 
 def hamiltonian(U, p, inv_mass=None) -> float:

@@ -138,7 +138,7 @@ class MaskedPosterior:
     """The conditional posterior of Sec. 3.2: Theta_~s fixed at the given
     values, U and its gradient as functions of Theta_s only."""
 
-    def __init__(self, kind, widths_a, widths_b, theta_fixed, sel, data, prior_sd, lik_sd):
+    def __init__(self, kind, widths_a, widths_b, theta_fixed, sel, data, prior_sd, lik_sd, prior_weight=1.0):
         self.kind = kind
         self.widths_a = list(widths_a)
         self.widths_b = None if widths_b is None else list(widths_b)
@@ -150,6 +150,7 @@ class MaskedPosterior:
         self.data = data
         self.prior_sd = float(prior_sd)
         self.lik_sd = float(lik_sd)
+        self.prior_weight = float(prior_weight)   # the share of the prior term this potential carries
 
     def full(self, theta_s):
         th = self.theta_fixed.copy()
@@ -163,10 +164,33 @@ class MaskedPosterior:
         theta_s = np.asarray(theta_s, dtype=np.float64)
         U_lik, g_full = likelihood_and_grad(self.kind, self.widths_a, self.widths_b,
                                             self.full(theta_s), self.data, self.lik_sd)
-        inv_pv = 1.0 / (self.prior_sd * self.prior_sd)
+        inv_pv = self.prior_weight / (self.prior_sd * self.prior_sd)
         U = U_lik + 0.5 * inv_pv * float(np.sum(theta_s * theta_s))
         g = g_full[self.sel] + inv_pv * theta_s
         return U, g
+
+
+def batch_posteriors(post, bounds):
+    """The split of a posterior's potential over consecutive data batches used
+    by symmetric-splitting HMC (Sec. 4.2.3's full-HMC baseline): batch m holds
+    the data rows bounds[m] <= i < bounds[m+1] (MLP rows; DeepONet input
+    functions, each with all its query points) and 1/M of the prior term, so
+    that the batch potentials add up to U."""
+    bounds = [int(b) for b in bounds]
+    M = len(bounds) - 1
+    if M < 1 or bounds[0] != 0 or any(b1 <= b0 for b0, b1 in zip(bounds, bounds[1:])):
+        raise ValueError("bounds must start at 0 and increase strictly")
+    keys = ("x", "y") if post.kind == "mlp" else ("u", "v")
+    if bounds[-1] != post.data[keys[0]].shape[0]:
+        raise ValueError("bounds must end at the number of data rows")
+    out = []
+    for b0, b1 in zip(bounds, bounds[1:]):
+        data = dict(post.data)
+        for k in keys:
+            data[k] = post.data[k][b0:b1]
+        out.append(MaskedPosterior(post.kind, post.widths_a, post.widths_b, post.theta_fixed, post.sel, data,
+                                   post.prior_sd, post.lik_sd, prior_weight=post.prior_weight / M))
+    return out
 
 
 def data_from_workload(w):
