@@ -280,7 +280,12 @@ int pick_threads(size_t /*lds*/, int forced) {
 // layers, where slab 3 holds a hidden activation.
 // Slabs 1 and 3 may share LDS in towers of four or more layers, at tile
 // heights of at most 32 rows (the 64-row kernels carry no recompute code).
-bool can_alias(const std::vector<int>& w, int r) { return w.size() >= 5 && r <= 32; }
+// Slab sharing needs four or more layers; the kernels carry its recompute
+// code at tiles of at most 32 rows, and at 64 rows in BF16 (the 256-wide
+// MLP fits 64-row BF16 tiles only with it: 22 against 34 ms at 32 rows).
+bool can_alias(const std::vector<int>& w, int r, int prec) {
+    return w.size() >= 5 && (r <= 32 || prec == HMC_BF16);
+}
 
 // LDS row stride (elements) of slab l.
 int slab_ld(const std::vector<int>& w, int prec, size_t l) { return roundup(w[l], pad_of(prec)) + lpad_of(prec); }
@@ -374,9 +379,9 @@ int pick_rows(const std::vector<int>& w, int prec, size_t extra_per_row, size_t 
     const bool force_alias = rc && !std::strcmp(rc, "1");
     // the sharing choice for one candidate height; false: it does not fit
     auto choose = [&](int r, bool& al) {
-        if (force_alias && can_alias(w, r)) { al = true; return fits_as(r, true); }
+        if (force_alias && can_alias(w, r, prec)) { al = true; return fits_as(r, true); }
         if (fits_as(r, false)) { al = false; return true; }
-        if (can_alias(w, r) && fits_as(r, true)) { al = true; return true; }
+        if (can_alias(w, r, prec) && fits_as(r, true)) { al = true; return true; }
         return false;
     };
     if (forced) return choose(forced, alias) ? forced : 0;

@@ -1123,9 +1123,10 @@ __device__ __forceinline__ void tower_backward(const GradArgs& a, const TowerPla
     const int* bseg = m->bseg;
     const unsigned dmask = m->dmask;
     for (int l = tp.nl - 1; l >= lowest; --l) {
-        // (slab sharing is planned for tiles of at most 32 rows only, so the
-        // 64-row instances carry no recompute code and its registers)
-        if constexpr (R <= 32) {
+        // (slab sharing is planned for tiles of at most 32 rows, and for
+        // BF16 at 64 rows, so the other 64-row instances carry no recompute
+        // code and its registers)
+        if constexpr (R <= 32 || P == 2) {
             if (l == 1 && tp.rc1) {
                 // the barrier that ended layer 2's adjoint product has
                 // retired every read of slab 3 (delta_3)
