@@ -284,39 +284,47 @@ TRAJ_KERNELS = ("k_traj_begin<", "k_mlp_grad<", "k_branch_grad<", "k_trunk_fwd<"
 
 
 def trajectory_gaps(trace_csv):
-    """Idle time between the kernels of the trajectory graphs, from the
-    rocprofv3 kernel trace: consecutive dispatches of the trajectory kernels
-    on one queue that belong to one trajectory (from its k_traj_begin to its
-    k_traj_end), the device idle between the end of one and the start of the
-    next summed, against the kernels' own time over the same trajectories."""
+    """Idle time of the device inside the trajectory graphs, from the
+    rocprofv3 kernel trace: over each trajectory's span (the start of its
+    k_traj_begin to the end of its k_traj_end) the union of the trajectory
+    kernels' intervals on every queue (the graph may run two branches on two
+    queues at once), the idle time the span minus that union, and the gaps
+    between the union's stretches."""
     import csv
     rows = [r for r in csv.DictReader(open(trace_csv)) if any(k in r["Kernel_Name"] for k in TRAJ_KERNELS)]
-    rows.sort(key=lambda r: (r["Queue_Id"], int(r["Start_Timestamp"])))
-    busy = idle = 0
-    gaps, n_traj, open_traj, prev = [], 0, False, None
-    for r in rows:
-        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
-        name = r["Kernel_Name"]
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    spans, t_open = [], None
+    for t0, t1, name in iv:
         if "k_traj_begin<" in name:
-            open_traj, prev = True, None
-        if not open_traj:
-            continue
-        if prev is not None and prev[0] == r["Queue_Id"]:
-            g = max(t0 - prev[1], 0)
-            gaps.append(g)
-            idle += g
-        busy += t1 - t0
-        prev = (r["Queue_Id"], t1)
-        if "k_traj_end<" in name:
-            open_traj = False
-            n_traj += 1
-    if not gaps:
+            t_open = t0
+        elif "k_traj_end<" in name and t_open is not None:
+            spans.append((t_open, t1))
+            t_open = None
+    if not spans:
         return ["Trajectory gaps: no complete trajectory in the trace."]
-    g = np.array(gaps) / 1e3
-    return [f"Trajectory gaps over {n_traj} trajectories ({len(gaps) + n_traj} kernel dispatches): kernels busy "
-            f"{busy / 1e6:.3f} ms, idle between them {idle / 1e6:.3f} ms ({100 * idle / (busy + idle):.3f}% of the "
-            f"trajectories' span); gap per dispatch median {np.median(g):.2f} us, p90 {np.quantile(g, 0.9):.2f} us, "
-            f"max {g.max():.2f} us."]
+    covered = idle = kernel_time = dispatches = 0
+    gaps = []
+    for a, b in spans:
+        inside = [(max(t0, a), min(t1, b)) for t0, t1, _ in iv if t1 > a and t0 < b]
+        dispatches += len(inside)
+        kernel_time += sum(t1 - t0 for t0, t1 in inside)
+        end = a
+        for i, (t0, t1) in enumerate(inside):   # sorted by start
+            if i:
+                gaps.append(max(t0 - end, 0))
+            if t0 > end:
+                idle += t0 - end
+            end = max(end, t1)
+        idle += max(b - end, 0)
+        covered += (b - a)
+    covered -= idle
+    g = np.array(gaps or [0]) / 1e3
+    return [f"Trajectory gaps over {len(spans)} trajectories ({dispatches} kernel dispatches): kernels cover "
+            f"{covered / 1e6:.3f} ms of the trajectories' span, the device is idle {idle / 1e6:.3f} ms between "
+            f"them ({100 * idle / (covered + idle):.3f}%); gap per dispatch median {np.median(g):.2f} us, p90 "
+            f"{np.quantile(g, 0.9):.2f} us, max {g.max():.2f} us; kernel time summed over queues "
+            f"{kernel_time / 1e6:.3f} ms, {kernel_time / max(covered, 1):.3f}x the covered time "
+            f"(above 1 where kernels on different queues ran at once)."]
 
 
 def sensitivity_flops(widths, rows):
@@ -721,6 +729,9 @@ def main():
                     help="run --config's workload at another precision (a comparison, not the headline line)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shapes with the library's autotuner (untimed) instead of its heuristic")
+    ap.add_argument("--split-rows", type=int, default=0, metavar="ROWS",
+                    help="symmetric-splitting HMC over data batches of ROWS rows (MLP workloads; "
+                         "a multiple of the rows per tile), for adaptation and the timed run")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s comparison with plain FP32 HMC")
     ap.add_argument("--ess-budget", type=float, default=130.0, help="seconds of plain FP32 HMC per ESS leg")
     ap.add_argument("--ess-only", nargs="*", metavar="WORKLOAD",
@@ -777,6 +788,12 @@ def main():
     s = Sampler.from_workload(w, seed=2507, tuning=tuning)
     progress(f"engine ready ({s.info['device_bytes'] / 2**30:.2f} GiB on the device)")
     C, L = w.n_chains, w.L
+    integrator = {"kind": "leapfrog", "grad_evals_per_trajectory": L}
+    if args.split_rows:
+        s.set_split(args.split_rows)
+        integrator = {"kind": "symmetric split", "batch_rows": args.split_rows,
+                      "batches": -(-w.n_rows() // args.split_rows), "grad_evals_per_trajectory": L + 1}
+        progress(f"symmetric splitting over {integrator['batches']} batches of {args.split_rows} rows")
     st_dtype = torch.float64 if w.precision == "fp64" else torch.float32
     out = torch.empty((args.steps, w.nnz), dtype=st_dtype, device="cuda")
     warm = torch.empty((max(args.warmup, 1), w.nnz), dtype=st_dtype, device="cuda")
@@ -829,7 +846,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "net": w.kind, "widths_a": w.widths_a, "widths_b": w.widths_b,
                    "rows": w.n_rows(), "chains": C, "selected_per_chain": selected_per_chain(w), "L": L,
-                   "products": w.precision, "energy": w.energy,
+                   "products": w.precision, "energy": w.energy, "integrator": integrator,
                    "eps_start": w.eps, "eps_adapt_iters": args.adapt,
                    "eps_calibration": args.calibrate,
                    "eps_median": float(np.median(eps_c)), "eps_min": float(np.min(eps_c)),

@@ -244,6 +244,25 @@ hmc_status hmc_grad(hmc_ctx* ctx, double* U, void* g);
 hmc_status hmc_trajectory(hmc_ctx* ctx, const void* p0, const double* eps, int32_t L,
                           void* theta_out, void* p_out, double* H0, double* H1);
 
+/* Symmetric-splitting HMC, the integrator of the paper's full-HMC baseline
+ * (Sec. 4.2.3, after Cobb and Jalaian): the data rows are split into
+ * consecutive batches of batch_rows rows (the last one takes the rest); the
+ * potential of a batch is its rows' likelihood plus 1/M of the prior (M
+ * batches), and every step of hmc_leapfrog, hmc_sample, hmc_trajectory,
+ * hmc_adapt and hmc_calibrate applies each batch gradient as a half kick of
+ * its own, in batch order, then drifts, then applies the batch half kicks
+ * in the mirrored order.  In exact arithmetic this is the leapfrog step;
+ * the trajectory takes L + 1 gradient evaluations (the batch gradients at
+ * the start are evaluated afresh).  batch_rows = 0 returns to plain
+ * leapfrog.
+ * Errors: HMC_EINVAL if batch_rows is negative, not a multiple of
+ * rows_per_tile_a (hmc_get_info), or gives more than 16 batches;
+ * HMC_EUNSUPPORTED for a DeepONet (its trunk gradient is reduced over every
+ * input function inside a row tile) and for an MLP engine with tile groups
+ * (HMC_TILE_GROUP above 1, or the automatic choice on large FP32 grids at
+ * 32 rows per tile). */
+hmc_status hmc_set_split(hmc_ctx* ctx, int64_t batch_rows);
+
 /* The momentum p ~ N(0, M) that the refresh of Algorithm 2 draws at
  * iteration `iteration`, for every chain (state type, host or device,
  * [nnz]).  The engine state is unchanged. */

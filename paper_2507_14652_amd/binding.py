@@ -28,7 +28,7 @@ ABI_FUNCTIONS = (
     "hmc_get_state", "hmc_set_state", "hmc_counters", "hmc_get_info", "hmc_time_kernels",
     "hmc_sync", "hmc_last_error", "hmc_destroy", "hmc_sensitivity", "hmc_select_mask",
     "hmc_predict", "hmc_init_tuned", "hmc_autotune", "hmc_adapt", "hmc_trajectory_length", "hmc_predict_noalloc",
-    "hmc_calibrate",
+    "hmc_calibrate", "hmc_set_split",
 )
 
 
@@ -95,6 +95,7 @@ def load():
         "hmc_momentum": [P, c_uint64, P],
         "hmc_get_state": [P, P, POINTER(c_double), POINTER(c_uint64)],
         "hmc_set_state": [P, P, POINTER(c_uint64)],
+        "hmc_set_split": [P, c_int64],
         "hmc_counters": [P, POINTER(c_int64), POINTER(c_int64)],
         "hmc_get_info": [P, POINTER(Info)],
         "hmc_time_kernels": [P, c_int32, POINTER(c_double)],
@@ -337,6 +338,11 @@ class Sampler:
         self._check(self._lib.hmc_trajectory(self._ctx, _ptr_of(p), _dptr(e), int(L), _ptr_of(th),
                                              _ptr_of(po), _dptr(H0), _dptr(H1)))
         return th, po, H0, H1
+
+    def set_split(self, batch_rows):
+        """Symmetric-splitting HMC over data batches of batch_rows rows
+        (hmc_set_split); 0 returns to plain leapfrog."""
+        self._check(self._lib.hmc_set_split(self._ctx, int(batch_rows)))
 
     def momentum(self, iteration):
         out = self._state_tensor()

@@ -119,6 +119,10 @@ struct hmc_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
+    // staggered chain halves in the trajectory graph (halves_on)
+    hipStream_t cap_stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_stag = nullptr, ev_join = nullptr;
+    int halves = 0;
 
     int kind = 0, prec = 0;
     TowerHost A, B;
@@ -279,10 +283,9 @@ int pick_threads(size_t /*lds*/, int forced) {
 // Slab sharing (recompute) applies to towers with at least four linear
 // layers, where slab 3 holds a hidden activation.
 // Slabs 1 and 3 may share LDS in towers of four or more layers, at tile
-// heights of at most 32 rows (the 64-row kernels carry no recompute code).
-// Slab sharing needs four or more layers; the kernels carry its recompute
-// code at tiles of at most 32 rows, and at 64 rows in BF16 (the 256-wide
-// MLP fits 64-row BF16 tiles only with it: 22 against 34 ms at 32 rows).
+// heights of at most 32 rows, and at 64 rows in BF16 (the other 64-row
+// kernels carry no recompute code; the 256-wide BF16 MLP fits 64-row tiles
+// only with sharing: 22 against 34 ms at 32 rows).
 bool can_alias(const std::vector<int>& w, int r, int prec) {
     return w.size() >= 5 && (r <= 32 || prec == HMC_BF16);
 }
@@ -513,11 +516,69 @@ hmc_status launch_refresh(hmc_ctx* x, hipStream_t s) {
 // the last one only: the energy pass reads it at theta_L.
 hmc_status launch_leapfrog(hmc_ctx* x, const StateArgs& sa, int L, hipStream_t s) {
     HMC_HIP(x, hmc_launch_traj_begin(x->prec, sa, s));
+    if (sa.split_n) {
+        // symmetric splitting: the batch kicks need the batch gradients at the
+        // start, so the trajectory takes L + 1 gradient evaluations
+        const int gx = (x->max_n + 255) / 256;
+        HMC_TRY(launch_grad(x, s));
+        HMC_HIP(x, hmc_launch_update_split(x->prec, sa, SPL_FIRST, gx, s));
+        for (int t = 1; t <= L; ++t) {
+            HMC_TRY(launch_grad(x, s));
+            const int mode = t == L ? SPL_END : t == L - 1 ? SPL_STEP_LAST : SPL_STEP;
+            HMC_HIP(x, hmc_launch_update_split(x->prec, sa, mode, gx, s));
+        }
+        return launch_energy(x, s);
+    }
     for (int t = 1; t <= L; ++t) {
         HMC_TRY(launch_grad(x, s));
         const int mode = t == L ? UPD_HALF_KICK : t == L - 1 ? UPD_KICK_DRIFT_LAST : UPD_KICK_DRIFT;
         HMC_HIP(x, hmc_launch_update(x->prec, sa, mode, update_grid(x), x->upd_sub, s));
     }
+    return launch_energy(x, s);
+}
+
+// Staggered chain halves: the trajectory graph runs the leapfrog steps of
+// chains [0, C/2) and [C/2, C) as two branches on two streams, the second
+// starting one gradient evaluation later, so that one half's partial sums
+// and kick (k_update, bound by HBM bandwidth) run beside the other half's
+// gradient kernel (bound by MFMA and LDS) instead of after it.  The chains
+// are independent, so every chain's arithmetic is unchanged.  MLP engines
+// with plain leapfrog, on grids where each half still has at least 16
+// workgroups per compute unit; HMC_HALVES=0 turns it off, =1 forces it.
+bool halves_on(const hmc_ctx* x) {
+    if (x->kind != HMC_MLP || x->sa.split_n || x->C < 2) return false;
+    const char* env = std::getenv("HMC_HALVES");
+    if (env && !std::strcmp(env, "0")) return false;
+    if (env && !std::strcmp(env, "1")) return true;
+    return (long long)(x->C / 2) * x->groups_a >= 16LL * 256;
+}
+
+hmc_status launch_leapfrog_halves(hmc_ctx* x, int L, hipStream_t s, hipStream_t s2) {
+    const StateArgs& sa = x->sa;
+    HMC_HIP(x, hmc_launch_traj_begin(x->prec, sa, s));
+    const int h = x->C / 2;
+    const int c0[2] = {0, h}, nc[2] = {h, x->C - h};
+    HMC_HIP(x, hipEventRecord(x->ev_fork, s));
+    HMC_HIP(x, hipStreamWaitEvent(s2, x->ev_fork, 0));
+    for (int b = 0; b < 2; ++b) {
+        hipStream_t st = b ? s2 : s;
+        GradArgs g = x->ga;
+        g.chain0 = c0[b];
+        g.n_chains = nc[b];
+        StateArgs u = sa;
+        u.chain0 = c0[b];
+        u.n_chains = nc[b];
+        const int grid = roundup(nc[b] * x->groups_a, 8);
+        if (b == 1) HMC_HIP(x, hipStreamWaitEvent(s2, x->ev_stag, 0));
+        for (int t = 1; t <= L; ++t) {
+            HMC_HIP(x, hmc_launch_mlp_grad(x->prec, x->Ra, x->nt_a, g, grid, x->lds_a, st));
+            if (b == 0 && t == 1) HMC_HIP(x, hipEventRecord(x->ev_stag, s));
+            const int mode = t == L ? UPD_HALF_KICK : t == L - 1 ? UPD_KICK_DRIFT_LAST : UPD_KICK_DRIFT;
+            HMC_HIP(x, hmc_launch_update(x->prec, u, mode, update_grid(x), x->upd_sub, st));
+        }
+    }
+    HMC_HIP(x, hipEventRecord(x->ev_join, s2));
+    HMC_HIP(x, hipStreamWaitEvent(s, x->ev_join, 0));
     return launch_energy(x, s);
 }
 
@@ -1140,6 +1201,10 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     HMC_HIP(x, hipEventCreate(&x->ev0));
     HMC_HIP(x, hipEventCreate(&x->ev1));
     HMC_HIP(x, hipStreamCreateWithFlags(&x->cap_stream, hipStreamNonBlocking));
+    HMC_HIP(x, hipStreamCreateWithFlags(&x->cap_stream2, hipStreamNonBlocking));
+    HMC_HIP(x, hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming));
+    HMC_HIP(x, hipEventCreateWithFlags(&x->ev_stag, hipEventDisableTiming));
+    HMC_HIP(x, hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming));
 
     // Scatter the starting positions and evaluate U and the gradient there.
     // A sensitivity engine samples nothing: its weights are theta0 already
@@ -1162,6 +1227,9 @@ void release(hmc_ctx* x) {
     if (x->ev0) (void)hipEventDestroy(x->ev0);
     if (x->ev1) (void)hipEventDestroy(x->ev1);
     if (x->cap_stream) (void)hipStreamDestroy(x->cap_stream);
+    if (x->cap_stream2) (void)hipStreamDestroy(x->cap_stream2);
+    for (hipEvent_t e : {x->ev_fork, x->ev_stag, x->ev_join})
+        if (e) (void)hipEventDestroy(e);
     if (x->own_stream && x->stream) (void)hipStreamDestroy(x->stream);
 }
 
@@ -1173,7 +1241,9 @@ hmc_status trajectory_graph(hmc_ctx* x, int L) {
     if (x->gexec) { (void)hipGraphExecDestroy(x->gexec); x->gexec = nullptr; }
     if (x->graph) { (void)hipGraphDestroy(x->graph); x->graph = nullptr; }
     HMC_HIP(x, hipStreamBeginCapture(x->cap_stream, hipStreamCaptureModeThreadLocal));
-    hmc_status st = launch_leapfrog(x, x->sa, L, x->cap_stream);
+    x->halves = halves_on(x);
+    hmc_status st = x->halves ? launch_leapfrog_halves(x, L, x->cap_stream, x->cap_stream2)
+                              : launch_leapfrog(x, x->sa, L, x->cap_stream);
     if (st == HMC_OK) {
         hipError_t e = hmc_launch_traj_end(x->prec, x->sa, END_METROPOLIS, x->cap_stream);
         if (e != hipSuccess) st = x->hip(e, "traj_end");
@@ -1941,6 +2011,35 @@ hmc_status hmc_set_state(hmc_ctx* x, const void* theta_s, const uint64_t* iterat
     HMC_HIP(x, hmc_launch_scatter_all(x->prec, x->sa, x->stream));
     HMC_TRY(launch_refresh(x, x->stream));
     HMC_HIP(x, hipStreamSynchronize(x->stream));
+    return HMC_OK;
+}
+
+hmc_status hmc_set_split(hmc_ctx* x, int64_t batch_rows) {
+    if (!x) return HMC_EINVAL;
+    if (batch_rows < 0) return x->fail(HMC_EINVAL, "batch_rows must be non-negative");
+    if (batch_rows == 0) {
+        x->sa.split_n = 0;
+    } else {
+        if (x->kind != HMC_MLP)
+            return x->fail(HMC_EUNSUPPORTED, "symmetric splitting needs an MLP (a DeepONet's trunk gradient sums over "
+                                             "every input function inside one row tile)");
+        if (x->tpg != 1)
+            return x->fail(HMC_EUNSUPPORTED, "symmetric splitting needs one partial slot per row tile (tile groups "
+                                             "are on: set HMC_TILE_GROUP=1)");
+        if (batch_rows % x->Ra)
+            return x->fail(HMC_EINVAL, "batch_rows must be a multiple of the rows per tile (" +
+                                           std::to_string(x->Ra) + ")");
+        const long long tb = batch_rows / x->Ra;
+        const long long M = (x->tiles_a + tb - 1) / tb;
+        if (M > HMC_SPLIT_MAX)
+            return x->fail(HMC_EINVAL, "at most " + std::to_string(HMC_SPLIT_MAX) + " batches (batch_rows too small)");
+        x->sa.split_n = (int)M;
+        for (int m = 0; m <= M; ++m) x->sa.split_t[m] = (int)std::min<long long>(m * tb, x->tiles_a);
+    }
+    // the captured trajectory follows the integrator
+    if (x->gexec) { (void)hipGraphExecDestroy(x->gexec); x->gexec = nullptr; }
+    if (x->graph) { (void)hipGraphDestroy(x->graph); x->graph = nullptr; }
+    x->graph_L = -1;
     return HMC_OK;
 }
 

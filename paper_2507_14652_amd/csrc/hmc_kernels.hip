@@ -1281,6 +1281,7 @@ __global__ __launch_bounds__(HMC_NT) __attribute__((amdgpu_waves_per_eu(MLP_WAVE
     const int groups = GROUP ? (a.tiles_a + tpg - 1) / tpg : a.tiles_a;
     int c, grp;
     if (!tile_of(a.n_chains * groups, groups, c, grp)) return;
+    c += a.chain0;
     if (!a.active[c]) return;
     const TowerPlan& tp = a.ta;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
@@ -1637,7 +1638,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode, int sub) {
     typedef typename PT<P>::A A; typedef typename PT<P>::S S;
     __shared__ A red[256];
-    const int c = blockIdx.y;
+    const int c = (int)blockIdx.y + s.chain0;
     if (!s.active[c]) return;
     const long long o = s.offs[c];
     const int n = (int)(s.offs[c + 1] - o);
@@ -1698,6 +1699,73 @@ __global__ __launch_bounds__(256) void k_update(const StateArgs s, int mode, int
     x = x + e * m * p;
     th[k] = x;
     scatter_to<P>(s, c, d0, d1, x, mode == UPD_KICK_DRIFT_LAST);
+}
+
+// Symmetric-splitting kicks (the full-HMC baseline integrator of Sec. 4.2.3,
+// after Cobb and Jalaian): the data rows form M consecutive batches of row
+// tiles, the potential of batch m is its rows' likelihood plus 1/M of the
+// prior, and each batch gradient reaches p as a half kick of its own, in
+// batch order before a drift and in the mirrored order after it.  One
+// thread per entry: it sums each batch's tile partials in tile order (eight
+// independent sums, combined in a fixed tree), keeps the M batch gradients
+// in registers and applies the kicks of `mode` (SPL_*).  The stored
+// gradient is the batch gradients added in batch order.
+template <int P>
+__global__ __launch_bounds__(256) void k_update_split(const StateArgs s, int mode) {
+    typedef typename PT<P>::A A; typedef typename PT<P>::S S;
+    const int c = blockIdx.y;
+    if (!s.active[c]) return;
+    const long long o = s.offs[c];
+    const int n = (int)(s.offs[c + 1] - o);
+    const int k = blockIdx.x * 256 + (int)threadIdx.x;
+    if (k >= n) return;
+    const int M = s.split_n;
+    S* th = reinterpret_cast<S*>(s.theta) + o;
+    S* mo = reinterpret_cast<S*>(s.mom) + o;
+    S x = th[k], p = mo[k];
+    const bool drift = mode != SPL_END;
+    int d0 = 0, d1 = 0;
+    if (drift) {
+        d0 = s.dst[2 * (o + k)];
+        d1 = s.dst[2 * (o + k) + 1];
+    }
+    const A* pp = reinterpret_cast<const A*>(s.part) + s.tmax * o + k;
+    const S prior = x * (S)(s.inv_prior_var / M);
+    S gb[HMC_SPLIT_MAX];
+    S gsum = (S)0;
+#pragma unroll
+    for (int m = 0; m < HMC_SPLIT_MAX; ++m) {
+        gb[m] = (S)0;
+        if (m >= M) continue;
+        A q[8] = {(A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0, (A)0};
+        int t = s.split_t[m];
+        const int t1 = s.split_t[m + 1];
+        for (; t + 7 < t1; t += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q[j] += pp[(size_t)(t + j) * n];
+        }
+        for (int j = 0; t < t1; ++t, ++j) q[j] += pp[(size_t)t * n];
+        gb[m] = (S)(((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]))) + prior;
+        gsum += gb[m];
+    }
+    reinterpret_cast<S*>(s.grad)[o + k] = gsum;
+    const S h = (S)0.5 * (S)s.eps[c];
+    if (mode != SPL_FIRST) {   // the mirrored half kicks closing a step
+#pragma unroll
+        for (int m = HMC_SPLIT_MAX - 1; m >= 0; --m)
+            if (m < M) p = p - h * gb[m];
+    }
+    if (mode != SPL_END) {     // the half kicks in batch order opening a step
+#pragma unroll
+        for (int m = 0; m < HMC_SPLIT_MAX; ++m)
+            if (m < M) p = p - h * gb[m];
+    }
+    mo[k] = p;
+    if (!drift) return;
+    const S mi = s.minv ? reinterpret_cast<const S*>(s.minv)[o + k] : (S)1;
+    x = x + (S)2 * h * mi * p;
+    th[k] = x;
+    scatter_to<P>(s, c, d0, d1, x, mode != SPL_STEP);
 }
 
 __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0, unsigned long long k1) {
@@ -1767,6 +1835,10 @@ __global__ __launch_bounds__(256) void k_traj_begin(const StateArgs s) {
             ths[k] = x;
             grs[k] = g;
             kin += 0.5 * (double)m * (double)p * (double)p;
+            if (s.split_n) {   // symmetric splitting: the batch kicks follow a fresh gradient
+                mo[k] = p;
+                continue;
+            }
             p = p - (S)0.5 * e * g;
             x = x + e * m * p;
             mo[k] = p;
@@ -2169,6 +2241,12 @@ hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int su
     HMC_DISPATCH_P(P, C_)
 #undef C_
 }
+hipError_t hmc_launch_update_split(int P, const StateArgs& s, int mode, int gx, hipStream_t st) {
+#define C_(p) hipLaunchKernelGGL((k_update_split<p>), dim3(gx, s.n_chains), dim3(256), 0, st, s, mode); return hipGetLastError()
+    HMC_DISPATCH_P(P, C_)
+#undef C_
+}
+
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st) {
 #define C_(p) hipLaunchKernelGGL((k_traj_begin<p>), dim3(s.n_chains), dim3(256), 0, st, s); return hipGetLastError()
     HMC_DISPATCH_P(P, C_)

@@ -26,6 +26,7 @@ hipError_t hmc_launch_combine_predict(int P, const void* Bn, const void* Tn, int
 hipError_t hmc_launch_zero(double* p, long long n, hipStream_t s);
 hipError_t hmc_launch_scatter_vec(int P, const StateArgs& sa, int c, const void* vec, long long n, hipStream_t s);
 hipError_t hmc_launch_update(int P, const StateArgs& s, int mode, int gx, int sub, hipStream_t st);
+hipError_t hmc_launch_update_split(int P, const StateArgs& s, int mode, int gx, hipStream_t st);
 hipError_t hmc_launch_traj_begin(int P, const StateArgs& s, hipStream_t st);
 hipError_t hmc_launch_traj_end(int P, const StateArgs& s, int mode, hipStream_t st);
 hipError_t hmc_launch_momentum(int P, const StateArgs& s, hipStream_t st);

@@ -66,7 +66,8 @@ struct GradArgs {
                                 // weight-gradient terms it sums into one partial slot
     int overlap;                // adjoint pass: a layer's weight gradient beside its adjoint
                                 // product's multiplies (epilogues after a barrier)
-    int n_chains;
+    int n_chains;               // chains of this launch: chain0 .. chain0 + n_chains - 1
+    int chain0;                 // (MLP gradient kernel; 0 elsewhere)
     const int* active;          // [C]
     const long long* offs;      // [C+1]
     const int* ecode;           // [nnz] (i << 16) | j, j = 0xFFFF for a bias
@@ -105,8 +106,13 @@ struct GradArgs {
 
 // Arguments of the per-entry kernels (reduction of partials, kicks, drifts,
 // scatter into the dense weights, momentum refresh, Metropolis step).
+// Most data batches of symmetric-splitting HMC (each batch's gradient is
+// held in a register of the update kernel).
+constexpr int HMC_SPLIT_MAX = 16;
+
 struct StateArgs {
-    int n_chains;
+    int n_chains;               // chains of this launch: chain0 .. chain0 + n_chains - 1
+    int chain0;                 // (k_update; 0 elsewhere)
     const int* active;
     const long long* offs;
     const int* seg;
@@ -149,6 +155,8 @@ struct StateArgs {
     void* stats;                // hmc_traj_stat [C]
     long long* n_acc;           // [C]
     long long* n_div;           // [C]
+    int split_n;                // symmetric splitting: data batches (0: plain leapfrog)
+    int split_t[HMC_SPLIT_MAX + 1];   // partial slots of batch m: split_t[m] <= t < split_t[m + 1]
 };
 
 // UPD_KICK_DRIFT_LAST: the last kick and drift of a trajectory, which also
@@ -156,6 +164,12 @@ struct StateArgs {
 // (earlier drifts leave that copy alone: nothing reads it before the drift
 // to theta_L).
 enum { UPD_GRAD = 0, UPD_KICK_DRIFT = 1, UPD_HALF_KICK = 2, UPD_KICK_DRIFT_LAST = 3 };
+// Symmetric-splitting kicks (k_update_split): SPL_FIRST, the batch half
+// kicks in batch order and the first drift; SPL_STEP, the mirrored half
+// kicks that end a step and the forward ones that start the next, then the
+// drift (SPL_STEP_LAST: the trajectory's last drift); SPL_END, the mirrored
+// half kicks that end the trajectory.
+enum { SPL_FIRST = 0, SPL_STEP = 1, SPL_STEP_LAST = 2, SPL_END = 3 };
 // Dense weight-gradient units: 2 x 2 or 4 x 2 blocks of 16 x 16, or the
 // interleaved BF16 4 x 2 unit (rows i0 + 16 g + 4 v + bi, columns j0 + 2 li + bj).
 enum { DWV_2X2 = 0, DWV_4X2 = 1, DWV_IL = 2 };

@@ -97,6 +97,7 @@ int main(void) {
         CHECK(hmc_sync(NULL) == HMC_EINVAL, "sync on null");
         CHECK(hmc_grad(NULL, &U, NULL) == HMC_EINVAL, "grad on null");
         CHECK(hmc_adapt(NULL, 1, &e, 1, 0.8, &e) == HMC_EINVAL, "adapt on null");
+        CHECK(hmc_set_split(NULL, 64) == HMC_EINVAL, "split on null");
         CHECK(hmc_get_info(NULL, &info) == HMC_EINVAL, "info on null");
         hmc_destroy(NULL);
     }

@@ -1,0 +1,39 @@
+"""The trajectory graph with staggered chain halves (the two halves of the
+chains as two graph branches, one gradient evaluation apart, so that one
+half's k_update runs beside the other half's gradient kernel) gives bitwise
+the samples and Metropolis records of the single-branch graph: the chains
+are independent and each chain's arithmetic is unchanged.  HMC_HALVES forces
+either form on a grid small enough to test; even and odd chain counts."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("chains", [4, 3])
+def test_halves_match_single_branch_bitwise(prec, chains, monkeypatch):
+    from paper_2507_14652_amd import Sampler
+    w = workloads.make("uneven_mlp_bf16", n_rows=700, n_chains=chains)
+    res = {}
+    for halves in ("0", "1"):
+        monkeypatch.setenv("HMC_HALVES", halves)
+        s = Sampler.from_workload(w, precision=prec, seed=11)
+        out = torch.empty((4, w.nnz), dtype=torch.float32, device="cuda")
+        _, st = s.sample(4, np.full(chains, w.eps), 7, out=out)
+        th, U, it = s.get_state()
+        res[halves] = (out.cpu().numpy(), st, th.cpu().numpy(), U, it)
+        s.close()
+    a, b = res["0"], res["1"]
+    print(f"{prec}, {chains} chains: acceptance {a[1]['accepted'].mean():.2f}")
+    assert 0 < a[1]["accepted"].mean()
+    np.testing.assert_array_equal(a[0], b[0])
+    for f in ("H0", "H1", "log_u", "accepted", "divergent"):
+        np.testing.assert_array_equal(a[1][f], b[1][f])
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
+    np.testing.assert_array_equal(a[4], b[4])
