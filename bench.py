@@ -92,6 +92,8 @@ def recorded_traffic(kernel, workload, instance=None):
 
 
 KERNEL_OF = {"mlp": "k_mlp_grad", "deeponet": "k_branch_grad"}
+PMC_TIMING_REPS = 5      # --timing-reps of the counter runs below
+TRACE_TIMING_REPS = 50   # bench.py's default --timing-reps (the trace run)
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_{w} -o bench -- "
              "python bench.py --config {w} --steps 5 --warmup 1 --adapt 5 --no-cpu-baseline --no-ess",
@@ -131,19 +133,47 @@ def energy_pass(kernel_name):
     return len(args) >= 3 and args[2].strip() == "true"
 
 
+def _grid(r):
+    if "Grid_Size" in r:
+        return int(r["Grid_Size"])
+    return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+
+
+def timed_dispatches(rows, reps):
+    """The rows (rocprofv3 trace or counter records) of the launches that
+    bench.py times with HIP events (Sampler.time_kernels: one warm-up launch
+    and `reps` timed ones, over the full grid with every chain active, the
+    last launches of each kernel in the process): per kernel instance, the
+    last reps + 1 dispatches of its largest grid.  The trajectory graphs
+    before them may launch a gradient kernel over half of the chains at a
+    time (staggered chain halves), and the step-size search with chains
+    inactive; neither is the launch the roofline prices."""
+    top, by = {}, {}
+    for r in rows:
+        top[r["Kernel_Name"]] = max(top.get(r["Kernel_Name"], 0), _grid(r))
+    for r in rows:
+        if _grid(r) == top[r["Kernel_Name"]]:
+            by.setdefault(r["Kernel_Name"], {}).setdefault(int(r["Dispatch_Id"]), []).append(r)
+    out = []
+    for d in by.values():
+        for k in sorted(d)[-(reps + 1):]:
+            out += d[k]
+    return out
+
+
 def _pmc_mean(csv_path, counter, name_part):
-    """Mean per dispatch of `counter` over the kernels whose name contains
-    name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch count.
-    Gradient kernels count only in their gradient form, not as the
+    """Mean per timed dispatch (timed_dispatches) of `counter` over the
+    kernels whose name contains name_part (KiB for FETCH_SIZE / WRITE_SIZE), and the dispatch
+    count.  Gradient kernels count only in their gradient form, not as the
     forward-only energy pass."""
     import csv
     vals, names = [], set()
     with open(csv_path) as f:
-        for r in csv.DictReader(f):
-            k = r["Kernel_Name"]
-            if r["Counter_Name"] == counter and name_part in k and not energy_pass(k):
-                vals.append(float(r["Counter_Value"]))
-                names.add(k.replace("void (anonymous namespace)::", ""))
+        rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]
+                and not energy_pass(r["Kernel_Name"])]
+    for r in timed_dispatches(rows, PMC_TIMING_REPS):
+        vals.append(float(r["Counter_Value"]))
+        names.add(r["Kernel_Name"].replace("void (anonymous namespace)::", ""))
     if not vals:
         raise SystemExit(f"no {counter} rows for {name_part} in {csv_path}")
     if len(names) != 1:
@@ -203,7 +233,8 @@ def record_mfma(workload, pmc_dir):
     import glob
     import workloads
     w = workloads.make(workload)
-    rows = list(csv.DictReader(open(glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0])))
+    rows = timed_dispatches(list(csv.DictReader(open(glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0]))),
+                            PMC_TIMING_REPS)
     names = ["k_mlp_grad<", "k_trunk_fwd<", "k_branch_grad<", "k_trunk_bwd<", "k_update<"]
     parts = {"k_mlp_grad<": None, "k_branch_grad<": "branch", "k_trunk_fwd<": None, "k_trunk_bwd<": None}
     main = main_kernel(w)
@@ -213,7 +244,8 @@ def record_mfma(workload, pmc_dir):
              "", "Command (repo root on the GPU box):", "  export TMPDIR=/tmp",
              "  " + PROFILE_CMDS["mfma"].format(w=workload), "",
              "busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs * 1024 SIMDs); "
-             "executed = MOPS * 512 flops (padding to the MFMA tiles included)",
+             "executed = MOPS * 512 flops (padding to the MFMA tiles included); over the launches bench.py times "
+             "(full grid, every chain active)",
              f"{'kernel':<42}{'dispatches':>11}{'busy %':>9}{'executed GFLOP':>16}{'algorithmic GFLOP':>19}"]
     for n in names:
         # one row per template instance (the gradient form and, where the
@@ -245,6 +277,7 @@ def record_trace(workload, trace_dir, bench_json=None, sens=False):
     """Writes profiles/<kernel>_<workload>_kernel_trace.txt from the
     rocprofv3 --stats summary of the benchmark command (sens: of the
     sensitivity-pass command)."""
+    import csv
     import glob
     import workloads
     w = workloads.make(workload)
@@ -270,6 +303,18 @@ def record_trace(workload, trace_dir, bench_json=None, sens=False):
         lines.append(f"The same run's bench line: {json.dumps(b)}")
     elif bench_json:
         b = json.loads([ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1])
+        main = main_kernel(w)
+        trace = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])))
+        sel = [r for r in trace if main in r["Kernel_Name"] and not energy_pass(r["Kernel_Name"])]
+        full = timed_dispatches(sel, TRACE_TIMING_REPS)
+        dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in full]
+        inst = full[0]["Kernel_Name"].replace("void (anonymous namespace)::", "")
+        if min(_grid(r) for r in sel) < _grid(full[0]):
+            lines.append(f"The trajectory graphs launched {inst} over half of the chains at a time "
+                         f"(grid {min(_grid(r) for r in sel)} against {_grid(full[0])}), so the statistics "
+                         f"above mix those dispatches with the full-grid ones that bench.py times.")
+        lines.append(f"The {len(full)} launches of {inst} that bench.py times (the last full-grid ones): mean "
+                     f"{sum(dur) / len(dur) / 1e6:.4f} ms.")
         lines.append(f"HIP-event mean of {kern} measured inside bench.py in the same run: "
                      f"{b['kernel_ms']['grad_main']:.4f} ms (kernel_ms.grad_main).")
     if not sens:
