@@ -542,15 +542,19 @@ hmc_status launch_leapfrog(hmc_ctx* x, const StateArgs& sa, int L, hipStream_t s
 // starting one gradient evaluation later, so that one half's partial sums
 // and kick (k_update, bound by HBM bandwidth) run beside the other half's
 // gradient kernel (bound by MFMA and LDS) instead of after it.  The chains
-// are independent, so every chain's arithmetic is unchanged.  MLP engines
-// with plain leapfrog, on grids where each half still has at least 16
-// workgroups per compute unit; HMC_HALVES=0 turns it off, =1 forces it.
+// are independent, so every chain's arithmetic is unchanged.  Plain
+// leapfrog only, where each half's main gradient kernel still has at least
+// eight workgroups per compute unit (measured: 256-chain MLP +9%, 512-wide
+// DeepONet +2%; the 64-chain DeepONet, four per compute unit, lost 1%, and
+// the 8-chain 2-D MLP gained under 1%); HMC_HALVES=0 turns it off, =1
+// forces it.
 bool halves_on(const hmc_ctx* x) {
-    if (x->kind != HMC_MLP || x->sa.split_n || x->C < 2) return false;
+    if (x->sa.split_n || x->C < 2) return false;
     const char* env = std::getenv("HMC_HALVES");
     if (env && !std::strcmp(env, "0")) return false;
     if (env && !std::strcmp(env, "1")) return true;
-    return (long long)(x->C / 2) * x->groups_a >= 16LL * 256;
+    const long long per_chain = x->kind == HMC_MLP ? x->groups_a : x->tiles_a;
+    return (long long)(x->C / 2) * per_chain >= 8LL * 256;
 }
 
 hmc_status launch_leapfrog_halves(hmc_ctx* x, int L, hipStream_t s, hipStream_t s2) {
@@ -568,10 +572,17 @@ hmc_status launch_leapfrog_halves(hmc_ctx* x, int L, hipStream_t s, hipStream_t 
         StateArgs u = sa;
         u.chain0 = c0[b];
         u.n_chains = nc[b];
-        const int grid = roundup(nc[b] * x->groups_a, 8);
         if (b == 1) HMC_HIP(x, hipStreamWaitEvent(s2, x->ev_stag, 0));
         for (int t = 1; t <= L; ++t) {
-            HMC_HIP(x, hmc_launch_mlp_grad(x->prec, x->Ra, x->nt_a, g, grid, x->lds_a, st));
+            if (x->kind == HMC_MLP) {
+                HMC_HIP(x, hmc_launch_mlp_grad(x->prec, x->Ra, x->nt_a, g, roundup(nc[b] * x->groups_a, 8),
+                                               x->lds_a, st));
+            } else {
+                const int ga = roundup(nc[b] * x->tiles_a, 8), gb = roundup(nc[b] * x->tiles_b, 8);
+                HMC_HIP(x, hmc_launch_trunk_fwd(x->prec, x->Rb, x->nt_b, g, gb, x->lds_b, st));
+                HMC_HIP(x, hmc_launch_branch_grad(x->prec, x->Ra, x->nt_a, g, ga, x->lds_a, st));
+                HMC_HIP(x, hmc_launch_trunk_bwd(x->prec, x->Rb, x->nt_b, g, gb, x->lds_b, st));
+            }
             if (b == 0 && t == 1) HMC_HIP(x, hipEventRecord(x->ev_stag, s));
             const int mode = t == L ? UPD_HALF_KICK : t == L - 1 ? UPD_KICK_DRIFT_LAST : UPD_KICK_DRIFT;
             HMC_HIP(x, hmc_launch_update(x->prec, u, mode, update_grid(x), x->upd_sub, st));

@@ -1449,6 +1449,7 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_fwd(const GradArgs a) {
     T* sm = reinterpret_cast<T*>(smem);
     int c, t;
     if (!tile_of(a.n_chains * a.tiles_b, a.tiles_b, c, t)) return;
+    c += a.chain0;
     if (!a.active[c]) return;
     const TowerPlan& tp = a.tb;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
@@ -1476,6 +1477,7 @@ __global__ __launch_bounds__(HMC_NT) void k_branch_grad(const GradArgs a) {
     double* red = reinterpret_cast<double*>(smem + a.red_off);
     int c, t;
     if (!tile_of(a.n_chains * a.tiles_a, a.tiles_a, c, t)) return;
+    c += a.chain0;
     if (!a.active[c]) return;
     const TowerPlan& tp = a.ta;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;
@@ -1532,6 +1534,7 @@ __global__ __launch_bounds__(HMC_NT) void k_trunk_bwd(const GradArgs a) {
     T* sm = reinterpret_cast<T*>(smem);
     int c, t;
     if (!tile_of(a.n_chains * a.tiles_b, a.tiles_b, c, t)) return;
+    c += a.chain0;
     if (!a.active[c]) return;
     const TowerPlan& tp = a.tb;
     const T* W = reinterpret_cast<const T*>(a.wbuf) + c * a.wstride;

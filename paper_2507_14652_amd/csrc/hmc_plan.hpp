@@ -67,7 +67,7 @@ struct GradArgs {
     int overlap;                // adjoint pass: a layer's weight gradient beside its adjoint
                                 // product's multiplies (epilogues after a barrier)
     int n_chains;               // chains of this launch: chain0 .. chain0 + n_chains - 1
-    int chain0;                 // (MLP gradient kernel; 0 elsewhere)
+    int chain0;                 // (gradient kernels; 0 elsewhere)
     const int* active;          // [C]
     const long long* offs;      // [C+1]
     const int* ecode;           // [nnz] (i << 16) | j, j = 0xFFFF for a bias

@@ -3,7 +3,8 @@ chains as two graph branches, one gradient evaluation apart, so that one
 half's k_update runs beside the other half's gradient kernel) gives bitwise
 the samples and Metropolis records of the single-branch graph: the chains
 are independent and each chain's arithmetic is unchanged.  HMC_HALVES forces
-either form on a grid small enough to test; even and odd chain counts."""
+either form on grids small enough to test; MLP and DeepONet, even and odd
+chain counts."""
 
 import numpy as np
 import pytest
@@ -14,11 +15,15 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 
+CASES = [("uneven_mlp_bf16", dict(n_rows=700)), ("antideriv_deeponet_bf16", dict(n_u=150, n_q=37))]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("chains", [4, 3])
-def test_halves_match_single_branch_bitwise(prec, chains, monkeypatch):
+@pytest.mark.parametrize("name,kw", CASES)
+def test_halves_match_single_branch_bitwise(name, kw, prec, chains, monkeypatch):
     from paper_2507_14652_amd import Sampler
-    w = workloads.make("uneven_mlp_bf16", n_rows=700, n_chains=chains)
+    w = workloads.make(name, n_chains=chains, **kw)
     res = {}
     for halves in ("0", "1"):
         monkeypatch.setenv("HMC_HALVES", halves)
@@ -29,7 +34,7 @@ def test_halves_match_single_branch_bitwise(prec, chains, monkeypatch):
         res[halves] = (out.cpu().numpy(), st, th.cpu().numpy(), U, it)
         s.close()
     a, b = res["0"], res["1"]
-    print(f"{prec}, {chains} chains: acceptance {a[1]['accepted'].mean():.2f}")
+    print(f"{name} {prec}, {chains} chains: acceptance {a[1]['accepted'].mean():.2f}")
     assert 0 < a[1]["accepted"].mean()
     np.testing.assert_array_equal(a[0], b[0])
     for f in ("H0", "H1", "log_u", "accepted", "divergent"):
@@ -37,3 +42,29 @@ def test_halves_match_single_branch_bitwise(prec, chains, monkeypatch):
     np.testing.assert_array_equal(a[2], b[2])
     np.testing.assert_array_equal(a[3], b[3])
     np.testing.assert_array_equal(a[4], b[4])
+
+
+def test_halves_at_full_size_match_single_branch_bitwise(monkeypatch):
+    """The 256-chain, 16,384-row MLP in the launch configuration the bench
+    times (FP32, 16-row tiles, the staggered halves chosen by the engine):
+    one Metropolis iteration of three leapfrog steps, bitwise against the
+    single-branch graph."""
+    from paper_2507_14652_amd import Sampler
+    w = workloads.make("uneven_mlp_bf16")
+    res = {}
+    for halves in ("0", None):
+        if halves is None:
+            monkeypatch.delenv("HMC_HALVES", raising=False)
+        else:
+            monkeypatch.setenv("HMC_HALVES", halves)
+        s = Sampler.from_workload(w, precision="fp32", seed=5)
+        assert s.info["rows_per_tile_a"] == 16
+        out = torch.empty((1, w.nnz), dtype=torch.float32, device="cuda")
+        _, st = s.sample(1, np.full(w.n_chains, w.eps), 3, out=out)
+        res[halves] = (out.cpu().numpy(), st)
+        s.close()
+    a, b = res["0"], res[None]
+    print(f"full size: acceptance {a[1]['accepted'].mean():.2f}")
+    np.testing.assert_array_equal(a[0], b[0])
+    for f in ("H0", "H1", "log_u", "accepted"):
+        np.testing.assert_array_equal(a[1][f], b[1][f])
