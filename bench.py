@@ -898,7 +898,7 @@ def main():
                    "eps_max": float(np.max(eps_c)),
                    "launch": {"autotuned": bool(args.autotune), "dw": (tuning or {}).get("dw", 0),
                               **{k: s.info[k] for k in ("rows_per_tile_a", "rows_per_tile_b", "threads_a",
-                                                        "threads_b")}}},
+                                                        "threads_b", "chain_halves")}}},
         "acceptance": acc,
         "kernel_ms": {"grad_main": ms[0], "trunk_fwd": ms[1], "trunk_bwd": ms[2], "reduce": ms[3]},
         "roofline": roof,

@@ -164,6 +164,11 @@ typedef struct {
     int32_t threads_a;        /* threads per workgroup of the MLP / branch   */
     int32_t threads_b;        /* ... and of the trunk tile kernels           */
     int32_t energy_precision; /* hmc_precision of the forward pass behind U  */
+    int32_t chain_halves;     /* 1: trajectory graphs run the two halves of  */
+                              /* the chains as two branches, one gradient    */
+                              /* evaluation apart (plain leapfrog on grids   */
+                              /* of at least eight workgroups per compute    */
+                              /* unit in each half; HMC_HALVES=0|1 overrides)*/
 } hmc_info_t;
 
 /* Creates an engine for the sampling problem of Algorithm 2 (Sec. 3.2: the

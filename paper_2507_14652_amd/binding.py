@@ -69,7 +69,8 @@ class Info(ctypes.Structure):
     _fields_ = [("n_params", c_int64), ("nnz", c_int64), ("n_chains", c_int32), ("precision", c_int32),
                 ("kind", c_int32), ("rows_per_tile_a", c_int32), ("rows_per_tile_b", c_int32),
                 ("tiles_a", c_int32), ("tiles_b", c_int32), ("device_bytes", c_int64),
-                ("threads_a", c_int32), ("threads_b", c_int32), ("energy_precision", c_int32)]
+                ("threads_a", c_int32), ("threads_b", c_int32), ("energy_precision", c_int32),
+                ("chain_halves", c_int32)]
 
 
 STAT_DTYPE = np.dtype([("H0", "f8"), ("H1", "f8"), ("log_u", "f8"), ("accepted", "i4"), ("divergent", "i4")])

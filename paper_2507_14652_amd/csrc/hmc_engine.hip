@@ -2079,6 +2079,7 @@ hmc_status hmc_get_info(const hmc_ctx* x, hmc_info_t* info) {
     info->threads_a = x->nt_a;
     info->threads_b = x->kind == HMC_DEEPONET ? x->nt_b : 0;
     info->energy_precision = x->energy32 ? x->eprec : x->prec;
+    info->chain_halves = halves_on(x) ? 1 : 0;
     return HMC_OK;
 }
 

@@ -59,6 +59,7 @@ def test_halves_at_full_size_match_single_branch_bitwise(monkeypatch):
             monkeypatch.setenv("HMC_HALVES", halves)
         s = Sampler.from_workload(w, precision="fp32", seed=5)
         assert s.info["rows_per_tile_a"] == 16
+        assert s.info["chain_halves"] == (0 if halves == "0" else 1)   # the engine's own choice at full size
         out = torch.empty((1, w.nnz), dtype=torch.float32, device="cuda")
         _, st = s.sample(1, np.full(w.n_chains, w.eps), 3, out=out)
         res[halves] = (out.cpu().numpy(), st)

@@ -78,6 +78,42 @@ def test_split_trajectory_matches_oracle(prec, n_rows, batches):
     s.close()
 
 
+@pytest.mark.parametrize("L", [1, 2])
+def test_short_split_trajectories_match_oracle(L):
+    """The kick modes at a trajectory's ends: L = 1 goes from the first batch
+    kicks straight to the closing ones, L = 2 has one interior step (the
+    last drift)."""
+    w = workloads.make("regress2d_fp32", n_rows=500, n_chains=2)
+    s = _sampler(w, precision="fp64", seed=3)
+    R, tiles = s.info["rows_per_tile_a"], s.info["tiles_a"]
+    batch_rows = -(-tiles // 3) * R
+    s.set_split(batch_rows)
+    p0 = np.random.default_rng(12).standard_normal(w.nnz)
+    th, p, H0, H1 = s.trajectory(p0, 3e-4, L)
+    th, p = th.double().cpu().numpy(), p.double().cpu().numpy()
+    s.close()
+    for c in range(w.n_chains):
+        post = on.posterior_for_chain(w, c)
+        batches = [b.potential_and_grad for b in on.batch_posteriors(post, _bounds(500, batch_rows))]
+        sl = slice(w.offs[c], w.offs[c + 1])
+        tr, pr, Ur, _ = oh.split_leapfrog(batches, w.chain_theta(c), p0[sl], 3e-4, L)
+        assert np.abs(th[sl] - tr).max() <= 1e-11 * np.abs(tr).max()
+        assert np.abs(p[sl] - pr).max() <= 1e-10 * np.abs(pr).max()
+        assert abs(H1[c] - (Ur + oh.kinetic(pr))) <= 1e-11 * abs(H1[c])
+
+
+def test_split_refused_with_tile_groups(monkeypatch):
+    monkeypatch.setenv("HMC_ROWS_A", "32")
+    monkeypatch.setenv("HMC_TILE_GROUP", "4")
+    w = workloads.make("uneven_mlp_bf16", n_rows=900, n_chains=2)
+    s = _sampler(w, precision="fp32")
+    assert s.info["rows_per_tile_a"] == 32
+    with pytest.raises(HMCError) as e:
+        s.set_split(32 * 8)
+    assert e.value.status == HMC_EUNSUPPORTED and "tile groups" in str(e.value)
+    s.close()
+
+
 def test_split_off_is_plain_leapfrog_and_split_equals_it_to_rounding():
     w = workloads.make("regress2d_fp32", n_rows=1000, n_chains=2)
     p0 = np.random.default_rng(9).standard_normal(w.nnz)
