@@ -70,3 +70,44 @@ def test_energy_pass_instances_are_told_apart():
     assert not bench.energy_pass("void (anonymous namespace)::k_mlp_grad<1, 32, false, true>(GradArgs)")
     assert not bench.energy_pass("void (anonymous namespace)::k_branch_grad<3, 32, false>(GradArgs)")
     assert not bench.energy_pass("void (anonymous namespace)::k_update<1>(StateArgs, int, int)")
+
+
+def _write_trace(path, rows):
+    cols = ["Kind", "Agent_Id", "Queue_Id", "Stream_Id", "Thread_Id", "Dispatch_Id", "Kernel_Id", "Kernel_Name",
+            "Correlation_Id", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
+    with open(path, "w") as f:
+        f.write(",".join(cols) + "\n")
+        for i, (q, name, t0, t1, grid) in enumerate(rows):
+            f.write(f"KERNEL_DISPATCH,1,{q},{q},1,{i + 1},1,\"{name}\",{i + 1},{t0},{t1},{grid},1,1\n")
+
+
+def test_trajectory_gaps_take_the_union_over_queues(tmp_path):
+    """Two branches on two queues: idle time is where no kernel of either
+    queue runs inside a trajectory's span, and the summed kernel time shows
+    the overlap."""
+    g, u = "k_mlp_grad<1, 16, false, false>(GradArgs)", "k_update<1>(StateArgs, int, int)"
+    rows = [(1, "k_traj_begin<1>(StateArgs)", 0, 1000, 8),
+            (1, g, 1000, 11000, 64), (2, g, 6000, 16000, 64),   # overlap 6000..11000
+            (1, u, 11000, 12000, 8), (2, u, 16500, 17000, 8),    # idle 16000..16500
+            (1, "k_traj_end<1>(StateArgs, int)", 17000, 18000, 8)]
+    p = tmp_path / "trace.csv"
+    _write_trace(p, rows)
+    line = bench.trajectory_gaps(str(p))[0]
+    assert "over 1 trajectories (6 kernel dispatches)" in line
+    assert "kernels cover 0.018 ms" in line           # 18000 - 500 ns covered
+    assert "idle 0.001 ms" in line                    # 500 ns
+    assert "1.343x the covered time" in line          # 23500 / 17500
+
+
+def test_timed_dispatches_are_the_last_full_grid_launches():
+    """The launches bench.py times are the last reps + 1 of each kernel's
+    largest grid; half-grid launches of the trajectory graphs and earlier
+    full-grid ones are left out."""
+    k = "k_mlp_grad<1, 16, false, false>(GradArgs)"
+    rows = []
+    did = 0
+    for grid in (64, 128, 128, 64, 64, 128, 128, 128):
+        did += 1
+        rows.append({"Kernel_Name": k, "Grid_Size": str(grid), "Dispatch_Id": str(did), "Counter_Value": str(did)})
+    got = bench.timed_dispatches(rows, 2)
+    assert [r["Dispatch_Id"] for r in got] == ["6", "7", "8"]
