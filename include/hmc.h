@@ -168,7 +168,8 @@ typedef struct {
                               /* the chains as two branches, one gradient    */
                               /* evaluation apart (plain leapfrog on grids   */
                               /* of at least eight workgroups per compute    */
-                              /* unit in each half; HMC_HALVES=0|1 overrides)*/
+                              /* unit in each half; HMC_HALVES=0|1, read at  */
+                              /* set-up, overrides)                          */
 } hmc_info_t;
 
 /* Creates an engine for the sampling problem of Algorithm 2 (Sec. 3.2: the

@@ -122,7 +122,7 @@ struct hmc_ctx {
     // staggered chain halves in the trajectory graph (halves_on)
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_stag = nullptr, ev_join = nullptr;
-    int halves = 0;
+    int halves = 0;               // halves_on, fixed at set-up and by hmc_set_split
 
     int kind = 0, prec = 0;
     TowerHost A, B;
@@ -1216,6 +1216,7 @@ hmc_status build(hmc_ctx* x, const hmc_net_desc* net, const hmc_mask_desc* mask,
     HMC_HIP(x, hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming));
     HMC_HIP(x, hipEventCreateWithFlags(&x->ev_stag, hipEventDisableTiming));
     HMC_HIP(x, hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming));
+    x->halves = halves_on(x) ? 1 : 0;
 
     // Scatter the starting positions and evaluate U and the gradient there.
     // A sensitivity engine samples nothing: its weights are theta0 already
@@ -1252,7 +1253,6 @@ hmc_status trajectory_graph(hmc_ctx* x, int L) {
     if (x->gexec) { (void)hipGraphExecDestroy(x->gexec); x->gexec = nullptr; }
     if (x->graph) { (void)hipGraphDestroy(x->graph); x->graph = nullptr; }
     HMC_HIP(x, hipStreamBeginCapture(x->cap_stream, hipStreamCaptureModeThreadLocal));
-    x->halves = halves_on(x);
     hmc_status st = x->halves ? launch_leapfrog_halves(x, L, x->cap_stream, x->cap_stream2)
                               : launch_leapfrog(x, x->sa, L, x->cap_stream);
     if (st == HMC_OK) {
@@ -2048,6 +2048,7 @@ hmc_status hmc_set_split(hmc_ctx* x, int64_t batch_rows) {
         for (int m = 0; m <= M; ++m) x->sa.split_t[m] = (int)std::min<long long>(m * tb, x->tiles_a);
     }
     // the captured trajectory follows the integrator
+    x->halves = halves_on(x) ? 1 : 0;
     if (x->gexec) { (void)hipGraphExecDestroy(x->gexec); x->gexec = nullptr; }
     if (x->graph) { (void)hipGraphDestroy(x->graph); x->graph = nullptr; }
     x->graph_L = -1;
@@ -2079,7 +2080,7 @@ hmc_status hmc_get_info(const hmc_ctx* x, hmc_info_t* info) {
     info->threads_a = x->nt_a;
     info->threads_b = x->kind == HMC_DEEPONET ? x->nt_b : 0;
     info->energy_precision = x->energy32 ? x->eprec : x->prec;
-    info->chain_halves = halves_on(x) ? 1 : 0;
+    info->chain_halves = x->halves;
     return HMC_OK;
 }
 
