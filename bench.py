@@ -635,7 +635,7 @@ def plain_torch_hmc(w, theta_s, eps, L, n_iter, seed, budget_s):
 
 ESS_COORDS = 256
 ESS_LEGS = {  # workload: engine iterations (adapt, burn-in, calibration rounds x batch, sampled)
-    "antideriv_deeponet_bf16": dict(adapt=200, burn=300, rounds=5, batch=120, n=1000),
+    "antideriv_deeponet_bf16": dict(adapt=200, burn=300, rounds=5, batch=120, n=2000),
     "regress2d_fp32": dict(adapt=500, burn=2000, rounds=8, batch=300, n=4000),
 }
 ESS_DEFAULT = ("antideriv_deeponet_bf16",)
