@@ -44,28 +44,36 @@ def test_halves_match_single_branch_bitwise(name, kw, prec, chains, monkeypatch)
     np.testing.assert_array_equal(a[4], b[4])
 
 
-def test_halves_at_full_size_match_single_branch_bitwise(monkeypatch):
-    """The 256-chain, 16,384-row MLP in the launch configuration the bench
-    times (FP32, 16-row tiles, the staggered halves chosen by the engine):
-    one Metropolis iteration of three leapfrog steps, bitwise against the
-    single-branch graph."""
+@pytest.mark.parametrize("name,eps", [("uneven_mlp_bf16", None), ("surface_deeponet_bf16", 2e-7)])
+def test_halves_at_full_size_match_single_branch_bitwise(name, eps, monkeypatch):
+    """The two workloads whose engines stagger the halves by themselves, at
+    full size in the launch configuration the bench times (the products
+    they sample in, 16-row tiles): the 256-chain, 16,384-row MLP and the
+    32-chain 512-wide DeepONet (FP64 energies; a step size near the one its
+    adaptation reaches, though from the unadapted start its proposals are
+    rejected).  One Metropolis iteration of three leapfrog steps, bitwise
+    against the single-branch graph: the end-point energies H1 carry the
+    whole trajectory whether or not the proposal is accepted."""
+    import dataclasses
     from paper_2507_14652_amd import Sampler
-    w = workloads.make("uneven_mlp_bf16")
+    w = workloads.make(name)
+    w = dataclasses.replace(w, precision=w.sample_precision or w.precision)
+    e = np.full(w.n_chains, eps or w.eps)
     res = {}
     for halves in ("0", None):
         if halves is None:
             monkeypatch.delenv("HMC_HALVES", raising=False)
         else:
             monkeypatch.setenv("HMC_HALVES", halves)
-        s = Sampler.from_workload(w, precision="fp32", seed=5)
+        s = Sampler.from_workload(w, seed=5)
         assert s.info["rows_per_tile_a"] == 16
         assert s.info["chain_halves"] == (0 if halves == "0" else 1)   # the engine's own choice at full size
-        out = torch.empty((1, w.nnz), dtype=torch.float32, device="cuda")
-        _, st = s.sample(1, np.full(w.n_chains, w.eps), 3, out=out)
+        out = torch.empty((1, w.nnz), dtype=s.state_dtype, device="cuda")
+        _, st = s.sample(1, e, 3, out=out)
         res[halves] = (out.cpu().numpy(), st)
         s.close()
     a, b = res["0"], res[None]
-    print(f"full size: acceptance {a[1]['accepted'].mean():.2f}")
+    print(f"{name} full size: acceptance {a[1]['accepted'].mean():.2f}")
     np.testing.assert_array_equal(a[0], b[0])
     for f in ("H0", "H1", "log_u", "accepted"):
         np.testing.assert_array_equal(a[1][f], b[1][f])
